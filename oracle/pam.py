@@ -1,0 +1,218 @@
+"""Algorithms 1 and 2 (PAM-FCTNLR / PAM-AFCTNLR) in float64 (oracle; test
+infrastructure).
+
+One sweep (Section 3.2, Algorithms 1-2): for each k in the sweep order,
+  M_k   = FCTN({A}, /A_k) unfolded as in Property 1 (eq. 4),
+  G     = M_k M_k^T, Y = X_(k) M_k^T + rho A_k^t (eq. 5),
+  A_k   = the eq. 8 solution, folded back by eq. 9;
+then X^{t+1} = P_Omega^c((FCTN(A^{t+1}) + rho X^t)/(1 + rho)) + P_Omega(Y) (eq. 10),
+stopping when ||X^{t+1} - X^t||_F / ||X^t||_F <= eps or after the sweep limit.
+
+Sub-networks are built by binary contractions of labelled tensors, each one
+counted as 2 * (output entries) * (contracted size) flops, so that the
+per-sweep counts can be checked against Tables 1-2:
+
+* reuse off (Algorithm 1): every M_k, and FCTN(A) for the X update, is a
+  chain contraction of the factors in increasing index order.
+* reuse on (Algorithm 2, Section 3.3): for N = 4 the pair tensors
+  A_3 x A_4 (contracted over R_34; shared by M_1 and M_2) and A_1 x A_2
+  (over R_12; shared by M_3 and M_4) are cached and rebuilt only when one of
+  their factors has changed; FCTN(A^{t+1}) is A_last times the sub-network of
+  the last-updated factor, which is then already current (M'_last).  For other
+  N only the X step is reused (Table 2 gives no M_k saving at N = 3).
+
+Sweep order (Algorithm 2's "unordered permutation"; Figure 6 is missing from
+the source): order_policy 0 keeps (1, .., N); order_policy 1 alternates
+(1, 2, 3, 4) and (3, 4, 1, 2) for N = 4, so that the pair built last in one
+sweep is still current for the first two updates of the next.  With reuse on
+this gives exactly Table 1's counts (t = 1: 4I^2R^5 + 8I^3R^5; t >= 2:
+2I^2R^5 + 8I^3R^5; X: 2I^4R^3).  For N != 4 policy 1 equals policy 0.
+
+Initial X is P_Omega(Y): the observed tensor is zero off Omega by definition
+of a partial observation (Section 1), so Algorithm 1's X^(1) = Y is read as
+P_Omega(Y); values of Y off Omega never enter any arithmetic.
+"""
+
+import numpy as np
+
+from . import tensor, laplacian, sylvester
+
+
+class FlopCounter:
+    """Per-category flop totals for the current sweep ('M', 'X', 'gram', 'rhs')."""
+
+    def __init__(self):
+        self.flops = {}
+
+    def add(self, cat, n):
+        self.flops[cat] = self.flops.get(cat, 0) + int(n)
+
+
+def _contract2(a, la, b, lb, out, counter, cat):
+    """Binary contraction of labelled tensors; counts 2*|out|*|contracted|."""
+    size = {}
+    for t, l in ((a, la), (b, lb)):
+        for ch, d in zip(l, t.shape):
+            size[ch] = d
+    shared = [c for c in la if c in lb and c not in out]
+    n_out = int(np.prod([size[c] for c in out], dtype=np.int64))
+    n_con = int(np.prod([size[c] for c in shared], dtype=np.int64)) if shared else 1
+    if counter is not None:
+        counter.add(cat, 2 * n_out * n_con)
+    return np.einsum(f"{la},{lb}->{out}", a, b, optimize=True)
+
+
+def _free_labels(N, group, labs):
+    """Labels that survive after contracting the factors in `group`: their
+    physical modes plus every bond to a factor outside the group."""
+    phys, bond = tensor._labels(N)
+    out = []
+    for j in sorted(group):
+        for ch in labs[j]:
+            if ch == phys[j]:
+                out.append(ch)
+            else:
+                other = [m for m in range(N) if m != j and bond[(j, m)] == ch][0]
+                if other not in group and ch not in out:
+                    out.append(ch)
+    return "".join(out)
+
+
+def chain(factors, members, counter, cat):
+    """Contract the factors in `members` one by one in increasing index order
+    (the from-scratch route of Algorithm 1).  Returns (tensor, labels)."""
+    N = len(factors)
+    labs = [tensor.factor_labels(N, j) for j in range(N)]
+    members = sorted(members)
+    T, lt = factors[members[0]], labs[members[0]]
+    for n, j in enumerate(members[1:], start=2):
+        out = _free_labels(N, members[:n], labs)
+        T = _contract2(T, lt, factors[j], labs[j], out, counter, cat)
+        lt = out
+    return T, lt
+
+
+def to_property1(T, lt, N, k):
+    """Permute a labelled M_k into Property 1's mode order and unfold it."""
+    order, rows, cols = tensor.subnetwork_modes(N, k)
+    T = np.einsum(f"{lt}->{order}", T)
+    return tensor.gunfold(T, rows, cols)
+
+
+class PairCache:
+    """Cached pair tensors for N = 4 (Section 3.3, Figures 2-3)."""
+
+    def __init__(self):
+        self.pairs = {}            # (p, q) -> (tensor, labels, versions)
+
+    def get(self, factors, versions, p, q, counter):
+        key = (p, q)
+        hit = self.pairs.get(key)
+        if hit is not None and hit[2] == (versions[p], versions[q]):
+            return hit[0], hit[1]
+        T, lt = chain(factors, [p, q], counter, "M")
+        self.pairs[key] = (T, lt, (versions[p], versions[q]))
+        return T, lt
+
+
+def subnetwork_M(factors, k, reuse, cache, versions, counter):
+    """M_k (Property 1 unfolding), with or without the reuse mechanism."""
+    N = len(factors)
+    if reuse and N == 4:
+        p, q = (2, 3) if k in (0, 1) else (0, 1)
+        P, lp = cache.get(factors, versions, p, q, counter)
+        other = [m for m in range(4) if m != k and m not in (p, q)][0]
+        labs = tensor.factor_labels(4, other)
+        out = _free_labels(4, [p, q, other], [tensor.factor_labels(4, j) for j in range(4)])
+        T = _contract2(P, lp, factors[other], labs, out, counter, "M")
+        return to_property1(T, out, N, k)
+    T, lt = chain(factors, [j for j in range(N) if j != k], counter, "M")
+    return to_property1(T, lt, N, k)
+
+
+def sweep_order(N, t, order_policy):
+    """Factor order for sweep t (0-based); see the module docstring."""
+    if order_policy == 1 and N == 4 and t % 2 == 1:
+        return [2, 3, 0, 1]
+    return list(range(N))
+
+
+def objective(X, factors, lam, delta):
+    """f = 1/2 ||X - FCTN(A)||^2 + sum_k lam_k/2 tr(A_k(k)^T L_k A_k(k))
+    (Section 3.4, f without the indicator, which is zero on feasible X)."""
+    Z = tensor.fctn(factors)
+    f = 0.5 * float(np.sum((X - Z) ** 2))
+    for k, A in enumerate(factors):
+        f += 0.5 * lam[k] * sylvester.trace_term(tensor.unfold(A, k), delta[k])
+    return f
+
+
+def x_update(X, Z, mask, rho):
+    """eq. 10 with X already equal to Y on Omega: a select, Y never re-read."""
+    return np.where(mask, X, (Z + rho * X) / (1.0 + rho))
+
+
+def complete(Y, mask, ranks, lam, delta, rho, sweeps, A0, tol=0.0, reuse=True,
+             order_policy=0, record_blocks=False, counters=None):
+    """Run PAM (Algorithm 1 if reuse is False, Algorithm 2 if True).
+
+    Y, mask: observed tensor and boolean Omega of shape I_1 x .. x I_N.
+    ranks: r_FCTN vector; lam, delta: per-mode lambda_k, delta_k; rho: proximal
+    weight; A0: initial factors (list of arrays with the factor shapes).
+    Returns (X, factors, stats) where stats holds per-sweep rel_change,
+    objective and, with record_blocks, the objective after every block.
+    counters: optional list that receives one FlopCounter per sweep.
+    """
+    Y = np.asarray(Y, dtype=np.float64)
+    mask = np.asarray(mask, dtype=bool)
+    N = Y.ndim
+    dims = Y.shape
+    lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), (N,))
+    delta = np.broadcast_to(np.asarray(delta, dtype=np.float64), (N,))
+    shapes = tensor.factor_shapes(dims, ranks)
+    factors = [np.array(a, dtype=np.float64).reshape(s) for a, s in zip(A0, shapes)]
+    X = np.where(mask, Y, 0.0)
+    cache = PairCache()
+    versions = [0] * N
+    stats = {"rel_change": [], "objective": [], "blocks": [], "sweeps_done": 0}
+
+    for t in range(sweeps):
+        counter = FlopCounter()
+        order = sweep_order(N, t, order_policy)
+        Mk = None
+        for k in order:
+            Mk = subnetwork_M(factors, k, reuse, cache, versions, counter)
+            Xk = tensor.unfold(X, k)
+            Ak = tensor.unfold(factors[k], k)
+            G = Mk @ Mk.T
+            counter.add("gram", 2 * Mk.shape[0] ** 2 * Mk.shape[1])
+            Yk = sylvester.rhs(Xk, Mk, Ak, rho)
+            counter.add("rhs", 2 * Xk.shape[0] * Mk.shape[0] * Mk.shape[1])
+            Anew = sylvester.solve_fast(G, Yk, lam[k], delta[k], rho)
+            factors[k] = tensor.fold(Anew, k, shapes[k])
+            versions[k] += 1
+            if record_blocks:
+                stats["blocks"].append(("A", k, objective(X, factors, lam, delta)))
+        last = order[-1]
+        if reuse:
+            Zl = tensor.unfold(factors[last], last) @ Mk
+            counter.add("X", 2 * Zl.shape[0] * Mk.shape[0] * Mk.shape[1])
+            Z = tensor.fold(Zl, last, dims)
+        else:
+            Z, lz = chain(factors, list(range(N)), counter, "X")
+        Xn = x_update(X, Z, mask, rho)
+        rel = float(np.linalg.norm(Xn - X) / np.linalg.norm(X))
+        X = Xn
+        f = 0.5 * float(np.sum((X - Z) ** 2))
+        for k in range(N):
+            f += 0.5 * lam[k] * sylvester.trace_term(tensor.unfold(factors[k], k), delta[k])
+        stats["rel_change"].append(rel)
+        stats["objective"].append(f)
+        stats["sweeps_done"] = t + 1
+        if record_blocks:
+            stats["blocks"].append(("X", -1, f))
+        if counters is not None:
+            counters.append(counter)
+        if tol > 0 and rel <= tol:
+            break
+    return X, factors, stats

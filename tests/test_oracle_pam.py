@@ -1,0 +1,206 @@
+"""Pins for the oracle's PAM loop (Algorithms 1-2): exact block-decrease
+identities (Section 3.4, condition 4), monotone objective, observed entries
+bit-exact, reuse on == reuse off, the Eckart-Young limit for N = 2, the
+stopping rule, and the per-sweep flop counts of Tables 1-2."""
+
+import numpy as np
+import pytest
+
+from oracle import pam, tensor, sylvester, laplacian, metrics
+from workloads import make_problem, init_factors, factor_shapes_of
+
+
+def _rand_problem(dims, ranks, sr=0.3, seed=0):
+    rng = np.random.default_rng(seed)
+    truth = rng.random(dims)
+    mask = rng.random(dims) < sr
+    Y = np.where(mask, truth, 0.0)
+    A0 = init_factors(rng, dims, ranks)
+    return truth, Y, mask, A0
+
+
+def _objective(X, fs, lam, delta):
+    return pam.objective(X, fs, [lam] * len(fs), [delta] * len(fs))
+
+
+@pytest.mark.parametrize("dims,ranks,k", [
+    ((6, 5, 4), (3, 2, 2), 0), ((6, 5, 4), (3, 2, 2), 2),
+    ((4, 3, 3, 5), (2, 2, 3, 1, 2, 2), 1), ((4, 3, 3, 5), (2, 2, 3, 1, 2, 2), 3),
+])
+def test_factor_block_exact_decrease(dims, ranks, k):
+    # f_old - f_new = rho ||D||^2 + 1/2 (tr(D G D^T) + lam tr(D^T L D)), D = A_new - A_old
+    lam, delta, rho = 0.3, 0.5, 0.1
+    _, Y, mask, A0 = _rand_problem(dims, ranks, seed=k)
+    X = np.where(mask, Y, 0.0)
+    fs = [a.copy() for a in A0]
+    f_old = _objective(X, fs, lam, delta)
+    M = tensor.subnetwork_unfolded(fs, k)
+    G = M @ M.T
+    A_old = tensor.unfold(fs[k], k)
+    A_new = sylvester.solve_fast(G, sylvester.rhs(tensor.unfold(X, k), M, A_old, rho), lam, delta, rho)
+    fs[k] = tensor.fold(A_new, k, fs[k].shape)
+    f_new = _objective(X, fs, lam, delta)
+    D = A_new - A_old
+    L = laplacian.matrix(dims[k], delta)
+    pred = rho * np.sum(D * D) + 0.5 * (np.trace(D @ G @ D.T) + lam * np.trace(D.T @ L @ D))
+    assert abs((f_old - f_new) - pred) <= 1e-9 * max(1.0, abs(f_old))
+    assert f_old - f_new >= rho * np.sum(D * D) * (1 - 1e-9)
+
+
+def test_x_block_exact_decrease():
+    # f(A, X_old) - f(A, X_new) = (1/2 + rho) ||X_new - X_old||^2 (eq. 10 is the prox step)
+    dims, ranks, rho = (5, 6, 4), (2, 3, 2), 0.1
+    _, Y, mask, A0 = _rand_problem(dims, ranks, seed=3)
+    X = np.where(mask, Y, 0.0)
+    Z = tensor.fctn(A0)
+    Xn = pam.x_update(X, Z, mask, rho)
+    f_old = 0.5 * np.sum((X - Z) ** 2)
+    f_new = 0.5 * np.sum((Xn - Z) ** 2)
+    assert abs((f_old - f_new) - (0.5 + rho) * np.sum((Xn - X) ** 2)) < 1e-10 * f_old
+
+
+@pytest.mark.parametrize("reuse", [False, True])
+@pytest.mark.parametrize("dims,ranks,policy", [
+    ((8, 7, 5), (3, 2, 2), 0),
+    ((5, 4, 3, 6), (2, 2, 3, 2, 2, 2), 1),
+])
+def test_objective_monotone_blockwise(reuse, dims, ranks, policy):
+    _, Y, mask, A0 = _rand_problem(dims, ranks, seed=1)
+    _, _, st = pam.complete(Y, mask, ranks, 1e-2, 0.5, 0.1, 6, A0, reuse=reuse,
+                            order_policy=policy, record_blocks=True)
+    vals = [v for (_, _, v) in st["blocks"]]
+    assert all(b <= a * (1 + 1e-12) + 1e-12 for a, b in zip(vals, vals[1:]))
+
+
+def test_observed_bit_exact_and_nan_off_omega():
+    dims, ranks = (6, 5, 4), (2, 2, 2)
+    truth, Y, mask, A0 = _rand_problem(dims, ranks, seed=2)
+    X1, f1, _ = pam.complete(Y, mask, ranks, 1e-2, 0.5, 0.1, 4, A0)
+    np.testing.assert_array_equal(X1[mask], Y[mask])
+    Ynan = np.where(mask, Y, np.nan)
+    X2, f2, _ = pam.complete(Ynan, mask, ranks, 1e-2, 0.5, 0.1, 4, A0)
+    np.testing.assert_array_equal(X1, X2)
+    for a, b in zip(f1, f2):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("dims,ranks,policy", [
+    ((9, 8, 5), (3, 2, 2), 0),
+    ((5, 4, 3, 6), (2, 2, 3, 2, 2, 2), 0),
+    ((5, 4, 3, 6), (2, 2, 3, 2, 2, 2), 1),
+])
+def test_reuse_on_equals_off(dims, ranks, policy):
+    _, Y, mask, A0 = _rand_problem(dims, ranks, seed=5)
+    Xa, fa, sa = pam.complete(Y, mask, ranks, 1e-2, 0.5, 0.1, 5, A0, reuse=False, order_policy=policy)
+    Xb, fb, sb = pam.complete(Y, mask, ranks, 1e-2, 0.5, 0.1, 5, A0, reuse=True, order_policy=policy)
+    assert np.linalg.norm(Xa - Xb) <= 1e-12 * np.linalg.norm(Xa)
+    for a, b in zip(fa, fb):
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(a)
+
+
+def test_order2_full_observation_reaches_eckart_young():
+    # N = 2, every entry observed, lambda = 0: PAM on ||X - A1 A2||^2 converges
+    # to the best rank-R approximation, whose error is the tail singular values
+    rng = np.random.default_rng(11)
+    I1, I2, R = 12, 10, 3
+    U, _ = np.linalg.qr(rng.standard_normal((I1, I1)))
+    V, _ = np.linalg.qr(rng.standard_normal((I2, I2)))
+    sig = np.array([10.0, 8.0, 6.0, 1.0, 0.5, 0.2, 0.1, 0.05, 0.02, 0.01])
+    Y = U[:, :10] @ np.diag(sig) @ V.T
+    mask = np.ones_like(Y, dtype=bool)
+    A0 = init_factors(rng, (I1, I2), (R,))
+    X, fs, st = pam.complete(Y, mask, (R,), 0.0, 0.5, 0.1, 400, A0)
+    err = np.linalg.norm(Y - fs[0] @ fs[1])
+    assert abs(err - np.sqrt(np.sum(sig[R:] ** 2))) < 1e-6
+
+
+def test_stopping_rule():
+    dims, ranks = (8, 7, 5), (2, 2, 2)
+    _, Y, mask, A0 = _rand_problem(dims, ranks, seed=6)
+    _, _, st = pam.complete(Y, mask, ranks, 1e-2, 0.5, 0.1, 500, A0, tol=1e-3)
+    assert st["sweeps_done"] < 500
+    assert st["rel_change"][-1] <= 1e-3
+    assert all(r > 1e-3 for r in st["rel_change"][:-1])
+
+
+def _counts(dims, ranks, reuse, policy, sweeps):
+    _, Y, mask, A0 = _rand_problem(dims, ranks, seed=7)
+    cs = []
+    pam.complete(Y, mask, ranks, 1e-2, 0.5, 0.1, sweeps, A0, reuse=reuse,
+                 order_policy=policy, counters=cs)
+    return [c.flops for c in cs]
+
+
+def test_table1_counts_order4():
+    # Table 1 (N = 4, every I and R equal): the printed per-sweep complexities
+    I, R = 6, 2
+    dims, ranks = (I,) * 4, (R,) * 6
+    alg1 = _counts(dims, ranks, False, 0, 3)
+    alg2 = _counts(dims, ranks, True, 1, 3)
+    for c in alg1:
+        assert c["M"] == 8 * (I**2 + I**3) * R**5
+        assert c["X"] == 2 * (I**2 + I**3) * R**5 + 2 * I**4 * R**3
+        assert c["gram"] + c["rhs"] == 8 * (I**3 * R**6 + I**4 * R**3)
+    assert alg2[0]["M"] == 4 * I**2 * R**5 + 8 * I**3 * R**5
+    for c in alg2[1:]:
+        assert c["M"] == 2 * I**2 * R**5 + 8 * I**3 * R**5
+    for c in alg2:
+        assert c["X"] == 2 * I**4 * R**3
+        assert c["gram"] + c["rhs"] == 8 * (I**3 * R**6 + I**4 * R**3)
+
+
+def test_table1_needs_the_alternating_order():
+    # with the fixed order (1,2,3,4) the cached pair A_1 x A_2 is stale at the
+    # start of every sweep, so t >= 2 costs as much as t = 1: the order
+    # alternation is what produces Table 1's t >= 2 row
+    I, R = 6, 2
+    c = _counts((I,) * 4, (R,) * 6, True, 0, 3)
+    assert c[1]["M"] == 4 * I**2 * R**5 + 8 * I**3 * R**5
+
+
+@pytest.mark.parametrize("N,I,R", [(3, 5, 2), (5, 3, 2)])
+def test_table2_counts_algorithm1(N, I, R):
+    dims, ranks = (I,) * N, (R,) * (N * (N - 1) // 2)
+    c = _counts(dims, ranks, False, 0, 1)[0]
+    m = 2 * N * sum(I**K * R**(K * (N - K) + K - 1) for K in range(2, N))
+    x = 2 * sum(I**K * R**(K * (N - K) + K - 1) for K in range(2, N + 1))
+    mm = 2 * N * (I**(N - 1) * R**(2 * (N - 1)) + I**N * R**(N - 1))
+    assert c["M"] == m and c["X"] == x and c["gram"] + c["rhs"] == mm
+
+
+def test_table2_x_count_algorithm2_order3():
+    I, R = 5, 2
+    c = _counts((I,) * 3, (R,) * 3, True, 0, 2)
+    for cc in c:
+        assert cc["X"] == 2 * I**3 * R**2
+        assert cc["M"] == 6 * I**2 * R**3     # no M saving at N = 3 (Table 2 rule)
+
+
+def test_psnr_definition():
+    truth = np.zeros((4, 5, 3))
+    recon = truth.copy()
+    recon[..., 0] += 0.1          # slice MSE 1e-2 -> 20 dB
+    recon[..., 1] += 0.01         # 1e-4 -> 40 dB
+    recon[..., 2] += 0.001        # 1e-6 -> 60 dB
+    assert abs(metrics.psnr(truth, recon) - 40.0) < 1e-9
+
+
+def test_generators_shapes_and_ranges():
+    p = make_problem("c1", seed=0)
+    assert p.Y.shape == (32, 32, 8) and p.Y.dtype == np.float64
+    assert 0.0 <= p.truth.min() and p.truth.max() <= 1.0
+    assert [a.shape for a in p.A0] == factor_shapes_of(p.dims, p.ranks)
+    assert abs(p.mask.mean() - 0.3) < 0.03
+    np.testing.assert_array_equal(p.Y[p.mask == 0], 0)
+    q = make_problem("c3", seed=1, dims=(24, 28, 3, 6))
+    assert q.Y.dtype == np.float32 and q.Y.shape == (24, 28, 3, 6)
+    r = make_problem("c4", seed=2, dims=(40, 36, 31))
+    assert r.truth.min() == 0.0 and r.truth.max() == 1.0
+
+
+def test_c1_quality_improves():
+    # on the low-rank C1 tensor the completion beats the zero-filled input
+    p = make_problem("c1", seed=0, sweeps=15)
+    X, _, st = pam.complete(p.Y, p.mask != 0, p.ranks, p.lam, p.delta, p.rho, p.sweeps, p.A0)
+    assert metrics.psnr(p.truth, X) > metrics.psnr(p.truth, p.Y) + 5.0
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(st["objective"], st["objective"][1:]))
