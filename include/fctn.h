@@ -1,0 +1,199 @@
+/*
+ * fctn.h - C ABI of libfctn.so: trace-regularized fully-connected tensor
+ * network (FCTN) tensor completion solved by proximal alternating
+ * minimization (PAM), on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation (arXiv 2510.22506, Section 3):
+ *   min over A_1..A_N, X of
+ *     1/2 ||X - FCTN(A_1..A_N)||_F^2 + sum_k lambda_k/2 tr(A_k(k)^T L_k A_k(k))
+ *   subject to P_Omega(X - Y) = 0                         (eq. model_1)
+ * solved by PAM sweeps (Algorithms 1-2): for each k the factor A_k solves the
+ * Sylvester equation A G + lambda_k L_k A + rho A = X_(k) M_k^T + rho A_k^t
+ * with G = M_k M_k^T and M_k the sub-network of the other factors
+ * (Property 1, eq. 4-9); then X = P_Omega^c((FCTN(A) + rho X)/(1 + rho))
+ * + P_Omega(Y) (eq. 10).  L_k is the periodic negative Laplacian
+ * (2 + delta_k) I - S - S^T (S the cyclic shift; positive definite).
+ *
+ * Conventions for every entry point
+ *   - Dense tensors (Y, X, Z, mask) are row-major ("C order": the last mode
+ *     varies fastest), prod(dims) elements, on the device.
+ *   - Factor A_k is row-major with the modes (R_1k, .., R_{k-1,k}, I_k,
+ *     R_{k,k+1}, .., R_kN) (Section 1, FCTN factor shapes).
+ *   - The rank vector is R_12, R_13, .., R_1N, R_23, .., R_{N-1,N}
+ *     (Section 1, r_FCTN).
+ *   - Storage type ("elem") of Y, X and Z is double for FCTN_F64 and float
+ *     for every other precision.
+ *   - All device pointers are caller-owned and must stay valid while the plan
+ *     uses them.  The library never allocates or frees device memory: all
+ *     its state lives in the caller's workspace `ws_dev`.
+ *   - Calls are asynchronous on the plan's HIP stream, except those that
+ *     fill host-side results (stats, flags); those synchronize the stream.
+ *   - Every call returns fctn_status; nothing throws across the boundary.
+ *     After FCTN_E_DEVICE the plan is unusable (the error is sticky).
+ *   - Calls on one plan are not thread-safe; distinct plans are independent.
+ */
+#ifndef FCTN_H
+#define FCTN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FCTN_MAX_ORDER 8
+#define FCTN_MAX_BONDS 28
+
+typedef enum {
+  FCTN_OK = 0,
+  FCTN_E_INVALID = 1,      /* bad descriptor, pointer, size or index      */
+  FCTN_E_NOMEM = 2,        /* workspace smaller than fctn_workspace_bytes */
+  FCTN_E_DEVICE = 3,       /* a HIP runtime call failed                   */
+  FCTN_E_NUMERIC = 4,      /* non-finite observed value on Omega          */
+  FCTN_E_UNSUPPORTED = 5   /* valid for the method, not for this build    */
+} fctn_status;
+
+typedef enum {
+  FCTN_F64 = 0,    /* every product and reduction in double                 */
+  FCTN_F32 = 1,    /* float contractions on MFMA, double reductions/solves  */
+  FCTN_BF16 = 2,   /* bf16 operands on MFMA, float accumulation             */
+  FCTN_BF16X3 = 3  /* split bf16 (hi*hi + hi*lo + lo*hi), float accumulation */
+} fctn_precision;
+
+typedef struct fctn_plan_s* fctn_plan_t;
+
+/* Problem descriptor: the inputs of Algorithms 1-2 apart from Y and Omega. */
+typedef struct {
+  int32_t order;                    /* N; this build runs N = 3 and N = 4    */
+  int64_t dims[FCTN_MAX_ORDER];     /* I_1 .. I_N, each >= 1                 */
+  int32_t ranks[FCTN_MAX_BONDS];    /* r_FCTN in the order above, each >= 1  */
+  double lambda[FCTN_MAX_ORDER];    /* lambda_k >= 0 (eq. model_1)           */
+  double delta[FCTN_MAX_ORDER];     /* delta_k > 0 (L_k, Section 3.1)        */
+  double rho;                       /* proximal weight rho > 0 (eq. 3)       */
+  int32_t precision;                /* fctn_precision                        */
+  int32_t reuse;                    /* 0: Algorithm 1 (every sub-network and
+                                       FCTN(A) from scratch); 1: Algorithm 2
+                                       (cached pair tensors, X from M'_last) */
+  int32_t order_policy;             /* 0: factor order 1..N every sweep;
+                                       1: for N = 4 alternate (1,2,3,4) and
+                                       (3,4,1,2) so a cached pair carries over
+                                       (Algorithm 2's permuted order)        */
+} fctn_desc;
+
+/* Per-sweep scalars (Algorithm 1 stopping rule; Section 3.4 objective f). */
+typedef struct {
+  double rel_change;   /* ||X^{t+1} - X^t||_F / ||X^t||_F                    */
+  double f_data;       /* 1/2 ||X^{t+1} - FCTN(A^{t+1})||_F^2                 */
+  double f_trace;      /* sum_k lambda_k/2 tr(A_k(k)^T L_k A_k(k))            */
+  double objective;    /* f_data + f_trace                                   */
+} fctn_sweep_stats;
+
+typedef struct {
+  int32_t sweeps_done;
+  double rel_change;
+  double objective;
+} fctn_stats;
+
+/* Exact device workspace (bytes) a plan for `desc` needs; 0 if the
+ * descriptor is invalid or unsupported. */
+size_t fctn_workspace_bytes(const fctn_desc* desc);
+
+/* Create a plan.  ws_dev: caller-owned device buffer of at least
+ * fctn_workspace_bytes(desc) bytes, 256-byte aligned; hip_stream: the
+ * hipStream_t all work is queued on (NULL = the null stream).  Builds the
+ * Fourier eigenbases of every L_k (eq. 7) on the device.  Factors start at
+ * zero until fctn_set_factors. */
+fctn_status fctn_plan(const fctn_desc* desc, void* ws_dev, size_t ws_bytes,
+                      void* hip_stream, fctn_plan_t* out);
+
+/* Initial factors (Algorithm 1, initialization: standard normal entries).
+ * A_host[k]: host pointer to factor k in float64 with the factor layout
+ * above.  Copied (synchronously) to the device; the working-precision copy is
+ * the round-to-nearest-even cast. */
+fctn_status fctn_set_factors(fctn_plan_t plan, const double* const* A_host);
+
+/* Observed data (Algorithm 1: X^(1) = Y, read as P_Omega(Y)).  Y_dev: elem
+ * tensor; mask_dev: uint8 tensor, nonzero = observed.  Values of Y off Omega
+ * are never read into arithmetic (they may be NaN).  Y and mask are copied
+ * into the workspace; the caller may free them afterwards.  Returns
+ * FCTN_E_NUMERIC (after a stream sync) if any observed value is not finite. */
+fctn_status fctn_set_observed(fctn_plan_t plan, const void* Y_dev,
+                              const uint8_t* mask_dev);
+
+/* Overwrite X (elem tensor on the device); for step-level checks. */
+fctn_status fctn_set_x(fctn_plan_t plan, const void* X_dev);
+
+/* Run `nsweeps` PAM sweeps (Algorithm 1 or 2 by desc.reuse).  If stats_host
+ * is not NULL it receives the scalars of the last sweep (synchronizes). */
+fctn_status fctn_sweep(fctn_plan_t plan, int32_t nsweeps,
+                       fctn_sweep_stats* stats_host);
+
+/* Run `nsweeps` sweeps on each of `count` independent plans, interleaving
+ * their launches across the plans' streams so that their work overlaps on the
+ * device (request batching).  Each plan's results equal those of fctn_sweep
+ * on that plan alone, bit for bit. */
+fctn_status fctn_sweep_many(fctn_plan_t* plans, int32_t count, int32_t nsweeps);
+
+/* Run up to max_sweeps sweeps, stopping after the first sweep whose relative
+ * change is <= tol (tol <= 0: exactly max_sweeps sweeps; the test runs every
+ * `check_every` sweeps, >= 1).  Copies X to X_out_dev if not NULL.  Fills
+ * stats_host if not NULL (synchronizes). */
+fctn_status fctn_complete(fctn_plan_t plan, int32_t max_sweeps, double tol,
+                          int32_t check_every, void* X_out_dev,
+                          fctn_stats* stats_host);
+
+/* Per-sweep history: the scalars of sweeps [first, first + count) counted
+ * from the plan's creation (at most the last 4096 sweeps are kept). */
+fctn_status fctn_get_history(fctn_plan_t plan, int32_t first, int32_t count,
+                             fctn_sweep_stats* out_host);
+
+/* Copy X (elem tensor) to dst_dev. */
+fctn_status fctn_get_x(fctn_plan_t plan, void* dst_dev);
+
+/* Copy the float64 master copy of factor k (factor layout) to dst_dev. */
+fctn_status fctn_get_factor(fctn_plan_t plan, int32_t k, double* dst_dev);
+
+/* ---- single steps of one sweep, on the plan's current state ------------
+ * For step-level checks and profiling; a sweep is these steps in order.   */
+
+/* Gram and right-hand side of eq. 5 for mode k from the current factors and
+ * X: G_dev (s_k x s_k) = M_k M_k^T and B_dev (I_k x s_k) = X_(k) M_k^T +
+ * rho A_k(k), both float64 row-major.  The s_k index is the bond multi-index
+ * of A_k in its mode order with the last bond fastest; the columns of M_k
+ * and X_(k) are the other physical indices, last fastest.  For N = 4 the
+ * needed pair tensor is (re)built first. */
+fctn_status fctn_step_gram_rhs(fctn_plan_t plan, int32_t k, double* G_dev,
+                               double* B_dev);
+
+/* Solve eq. 5 for mode k given G_dev, B_dev (layouts as above, float64) and
+ * store the result as factor k (eq. 8-9).  Returns tr(A^T L_k A) of the new
+ * factor in *trace_host if not NULL (synchronizes). */
+fctn_status fctn_step_solve(fctn_plan_t plan, int32_t k, const double* G_dev,
+                            const double* B_dev, double* trace_host);
+
+/* Z = FCTN(A_1..A_N) from the current factors, computed as
+ * A_k(k) M_k with M_k regenerated from the factors (X step of Algorithm 2,
+ * M'_k with k = last); written as an elem tensor to Z_dev. */
+fctn_status fctn_step_reconstruct(fctn_plan_t plan, int32_t k, void* Z_dev);
+
+/* eq. 10 on the plan's X with the given Z (elem tensor): X = Omega ? X :
+ * (Z + rho X)/(1 + rho).  stats_host (nullable) gets rel_change and f_data
+ * (f_trace and objective are 0; synchronizes). */
+fctn_status fctn_step_x_update(fctn_plan_t plan, const void* Z_dev,
+                               fctn_sweep_stats* stats_host);
+
+/* Sizes of the plan's unfoldings for mode k: s_k and I_k. */
+fctn_status fctn_mode_sizes(const fctn_desc* desc, int32_t k, int64_t* s_k,
+                            int64_t* I_k);
+
+/* Release the plan's host state (the workspace stays the caller's). */
+fctn_status fctn_destroy(fctn_plan_t plan);
+
+const char* fctn_status_str(fctn_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCTN_H */

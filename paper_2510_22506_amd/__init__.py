@@ -1,0 +1,11 @@
+"""MI355X-native trace-regularized FCTN tensor completion (PAM).
+
+The compute path is libfctn.so (hand-written HIP for gfx950, C ABI in
+include/fctn.h); ``fctn`` is its ctypes binding and ``serve`` a request
+loop on top of it.
+"""
+
+from .fctn import (  # noqa: F401
+    Plan, FctnError, make_desc, fctn_workspace_bytes, fctn_mode_sizes, fctn_status_str,
+    sweep_many, factor_shape, lib, LIB_PATH,
+)

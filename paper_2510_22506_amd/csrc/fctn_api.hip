@@ -1,0 +1,749 @@
+// Host side of libfctn.so: descriptor validation, workspace carving, the
+// per-mode operand tables, the sweep scheduler (Algorithms 1-2, including the
+// pair-tensor cache of the reuse mechanism and the alternating factor order)
+// and the C ABI declared in fctn.h.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "fctn.h"
+#include "kernels.hpp"
+
+using namespace fctn;
+
+namespace {
+
+constexpr int kHist = 4096;
+constexpr int kXBlocks = 1024;
+constexpr int kTilesPerGroup = 64;      // 4 waves x 16 tiles
+constexpr int kTargetGramWGs = 512;
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline int pad16(int x) { return (x + 15) / 16 * 16; }
+// leading dimension with ld % 64 == 16: conflict-free 16-lane x 4-row LDS reads
+inline int ld_pad(int x) { return x + ((16 - x % 64) % 64 + 64) % 64; }
+
+struct Carver {
+  char* base;
+  size_t off;
+  void* take(size_t bytes) {
+    off = align256(off);
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+enum Src { SRC_F0 = 0, SRC_P12 = 10, SRC_P34 = 11 };
+
+struct ModeInfo {
+  int64_t Ik, s, C, spost;
+  int u_src, v_src;
+  MGen mg;          // strides/sizes; U/V pointers resolved at launch
+  XView xv;
+  GramGeom geom;
+  int ncls;
+};
+
+}  // namespace
+
+struct fctn_plan_s {
+  fctn_desc d;
+  int N, prec;
+  int64_t dims[FCTN_MAX_ORDER];
+  int R[FCTN_MAX_ORDER][FCTN_MAX_ORDER];
+  int64_t numel;
+  size_t es;         // bytes per X element
+  hipStream_t st;
+  void* X;
+  void* Z;
+  uint32_t* bits;
+  int32_t* bad_part;
+  int bad_nblk;
+  double* A64[4];
+  void* Aw[4];
+  void* Au[4];
+  int64_t fnum[4];
+  void* P[2];
+  int64_t pnum[2];
+  PairDesc pd[2];
+  void* part;
+  double *G, *B, *At;
+  double* Q[4];
+  double* lamcol[4];
+  double* trace_part;
+  int max_cls;
+  double* lam_half;
+  int32_t* ncls_dev;
+  double* xpart;
+  double* hist;
+  double* scratch_slot;
+  ModeInfo mode[4];
+  int64_t sweeps_done;
+  int64_t fver[4];
+  int64_t pver[2][2];
+  bool pvalid[2];
+  fctn_status sticky;
+  bool debug;
+};
+
+namespace {
+
+fctn_status validate(const fctn_desc* d) {
+  if (!d) return FCTN_E_INVALID;
+  if (d->order < 2 || d->order > FCTN_MAX_ORDER) return FCTN_E_INVALID;
+  const int N = d->order;
+  for (int k = 0; k < N; ++k) {
+    if (d->dims[k] < 1) return FCTN_E_INVALID;
+    if (!(d->lambda[k] >= 0.0) || !(d->delta[k] >= 0.0)) return FCTN_E_INVALID;
+  }
+  for (int b = 0; b < N * (N - 1) / 2; ++b)
+    if (d->ranks[b] < 1) return FCTN_E_INVALID;
+  if (!(d->rho > 0.0)) return FCTN_E_INVALID;
+  if (d->precision < FCTN_F64 || d->precision > FCTN_BF16X3) return FCTN_E_INVALID;
+  if (d->reuse != 0 && d->reuse != 1) return FCTN_E_INVALID;
+  if (d->order_policy != 0 && d->order_policy != 1) return FCTN_E_INVALID;
+  if (N != 3 && N != 4) return FCTN_E_UNSUPPORTED;
+  if (d->precision != FCTN_F64 && d->precision != FCTN_F32) return FCTN_E_UNSUPPORTED;
+  return FCTN_OK;
+}
+
+void fill_ranks(const fctn_desc* d, int R[FCTN_MAX_ORDER][FCTN_MAX_ORDER]) {
+  const int N = d->order;
+  int b = 0;
+  for (int i = 0; i < N; ++i) {
+    R[i][i] = 0;
+    for (int j = i + 1; j < N; ++j) {
+      R[i][j] = R[j][i] = d->ranks[b++];
+    }
+  }
+}
+
+// Operand tables: M_k[ru * Rv + rv, cu * Cv + cv] = sum U[ru, cu, kap] V[rv, cv, kap]
+// where rows follow A_k's bond modes in order (last fastest) and columns the
+// other physical modes in order (last fastest); see the derivation per mode.
+void setup_modes(fctn_plan_s* P) {
+  const int N = P->N;
+  const int64_t* I = P->dims;
+  int(*R)[FCTN_MAX_ORDER] = P->R;
+  for (int k = 0; k < N; ++k) {
+    ModeInfo& m = P->mode[k];
+    m.Ik = I[k];
+    int64_t s = 1, spost = 1;
+    for (int j = 0; j < N; ++j)
+      if (j != k) s *= R[k][j];
+    for (int j = k + 1; j < N; ++j) spost *= R[k][j];
+    m.s = s;
+    m.spost = spost;
+    m.C = P->numel / I[k];
+    m.ncls = (int)(I[k] / 2 + 1);
+    MGen& g = m.mg;
+    XView& x = m.xv;
+    x.Ik = (int32_t)I[k];
+    if (N == 3) {
+      const int64_t I1 = I[0], I2 = I[1], I3 = I[2];
+      const int64_t R12 = R[0][1], R13 = R[0][2], R23 = R[1][2];
+      if (k == 0) {
+        m.u_src = SRC_F0 + 1; g.u_ru = I2 * R23; g.u_cu = R23; g.u_k = 1; g.Ru = (int)R12; g.K = (int)R23;
+        m.v_src = SRC_F0 + 2; g.v_rv = R23 * I3; g.v_cv = 1; g.v_k = I3; g.Rv = (int)R13;
+        g.Cu = I2; g.Cv = I3; x.x_cu = I3; x.x_cv = 1; x.x_ik = I2 * I3;
+      } else if (k == 1) {
+        m.u_src = SRC_F0 + 0; g.u_ru = R13; g.u_cu = R12 * R13; g.u_k = 1; g.Ru = (int)R12; g.K = (int)R13;
+        m.v_src = SRC_F0 + 2; g.v_rv = I3; g.v_cv = 1; g.v_k = R23 * I3; g.Rv = (int)R23;
+        g.Cu = I1; g.Cv = I3; x.x_cu = I2 * I3; x.x_cv = 1; x.x_ik = I3;
+      } else {
+        m.u_src = SRC_F0 + 0; g.u_ru = 1; g.u_cu = R12 * R13; g.u_k = R13; g.Ru = (int)R13; g.K = (int)R12;
+        m.v_src = SRC_F0 + 1; g.v_rv = 1; g.v_cv = R23; g.v_k = I2 * R23; g.Rv = (int)R23;
+        g.Cu = I1; g.Cv = I2; x.x_cu = I2 * I3; x.x_cv = I3; x.x_ik = 1;
+      }
+    } else {
+      const int64_t I1 = I[0], I2 = I[1], I3 = I[2], I4 = I[3];
+      const int64_t R12 = R[0][1], R13 = R[0][2], R14 = R[0][3];
+      const int64_t R23 = R[1][2], R24 = R[1][3], R34 = R[2][3];
+      const int64_t pb = R13 * R14 * R23 * R24;   // bond block of either pair tensor
+      if (k == 0) {
+        m.u_src = SRC_F0 + 1; g.u_ru = I2 * R23 * R24; g.u_cu = R23 * R24; g.u_k = 1;
+        g.Ru = (int)R12; g.K = (int)(R23 * R24);
+        m.v_src = SRC_P34; g.v_rv = R23 * R24; g.v_cv = pb; g.v_k = 1; g.Rv = (int)(R13 * R14);
+        g.Cu = I2; g.Cv = I3 * I4; x.x_cu = I3 * I4; x.x_cv = 1; x.x_ik = I2 * I3 * I4;
+      } else if (k == 1) {
+        m.u_src = SRC_F0 + 0; g.u_ru = R13 * R14; g.u_cu = R12 * R13 * R14; g.u_k = 1;
+        g.Ru = (int)R12; g.K = (int)(R13 * R14);
+        m.v_src = SRC_P34; g.v_rv = 1; g.v_cv = pb; g.v_k = R23 * R24; g.Rv = (int)(R23 * R24);
+        g.Cu = I1; g.Cv = I3 * I4; x.x_cu = I2 * I3 * I4; x.x_cv = 1; x.x_ik = I3 * I4;
+      } else if (k == 2) {
+        m.u_src = SRC_P12; g.u_ru = R14 * R24; g.u_cu = pb; g.u_k = 1;
+        g.Ru = (int)(R13 * R23); g.K = (int)(R14 * R24);
+        m.v_src = SRC_F0 + 3; g.v_rv = I4; g.v_cv = 1; g.v_k = R34 * I4; g.Rv = (int)R34;
+        g.Cu = I1 * I2; g.Cv = I4; x.x_cu = I3 * I4; x.x_cv = 1; x.x_ik = I4;
+      } else {
+        m.u_src = SRC_P12; g.u_ru = 1; g.u_cu = pb; g.u_k = R14 * R24;
+        g.Ru = (int)(R14 * R24); g.K = (int)(R13 * R23);
+        m.v_src = SRC_F0 + 2; g.v_rv = 1; g.v_cv = R34; g.v_k = I3 * R34; g.Rv = (int)R34;
+        g.Cu = I1 * I2; g.Cv = I3; x.x_cu = I3 * I4; x.x_cv = I4; x.x_ik = 1;
+      }
+    }
+  }
+  if (N == 4) {
+    const int64_t I1 = I[0], I2 = I[1], I3 = I[2], I4 = I[3];
+    const int64_t R12 = R[0][1], R13 = R[0][2], R14 = R[0][3];
+    const int64_t R23 = R[1][2], R24 = R[1][3], R34 = R[2][3];
+    PairDesc& a = P->pd[0];   // P12[(i1,i2)][(r13,r23)][(r14,r24)], contracted over r12
+    a.a_i = R12 * R13 * R14; a.a_1 = R14; a.a_2 = 1; a.a_k = R13 * R14;
+    a.b_i = R23 * R24; a.b_1 = R24; a.b_2 = 1; a.b_k = I2 * R23 * R24;
+    a.Ia = (int)I1; a.Ib = (int)I2; a.n1a = (int)R13; a.n2a = (int)R14; a.n1b = (int)R23;
+    a.n2b = (int)R24; a.K = (int)R12;
+    PairDesc& b = P->pd[1];   // P34[(i3,i4)][(r13,r14)][(r23,r24)], contracted over r34
+    b.a_i = R34; b.a_1 = R23 * I3 * R34; b.a_2 = I3 * R34; b.a_k = 1;
+    b.b_i = 1; b.b_1 = R24 * R34 * I4; b.b_2 = R34 * I4; b.b_k = I4;
+    b.Ia = (int)I3; b.Ib = (int)I4; b.n1a = (int)R13; b.n2a = (int)R23; b.n1b = (int)R14;
+    b.n2b = (int)R24; b.K = (int)R34;
+    P->pnum[0] = I1 * I2 * R13 * R14 * R23 * R24;
+    P->pnum[1] = I3 * I4 * R13 * R14 * R23 * R24;
+  }
+}
+
+bool setup_geom(ModeInfo& m, size_t es) {
+  GramGeom& g = m.geom;
+  g.s = (int)m.s;
+  g.sp = pad16(g.s);
+  g.Ik = (int)m.Ik;
+  g.ip = pad16(g.Ik);
+  g.nbj = g.sp / 16;
+  g.nG = g.nbj * (g.nbj + 1) / 2;
+  g.nB = (g.ip / 16) * g.nbj;
+  g.nTiles = g.nG + g.nB;
+  g.tilesPerGroup = kTilesPerGroup;
+  g.nGroups = (g.nTiles + kTilesPerGroup - 1) / kTilesPerGroup;
+  int xmax = 0;
+  for (int grp = 0; grp < g.nGroups; ++grp) {
+    const int t0 = grp * kTilesPerGroup, t1 = std::min(t0 + kTilesPerGroup, g.nTiles);
+    if (t1 > g.nG) {
+      const int bf = (std::max(t0, g.nG) - g.nG) / g.nbj, bl = (t1 - 1 - g.nG) / g.nbj;
+      xmax = std::max(xmax, (bl - bf + 1) * 16);
+    }
+  }
+  g.xrows = xmax;
+  g.ldm = ld_pad(g.sp);
+  g.ldx = ld_pad(std::max(xmax, 16));
+  g.tc = 0;
+  for (int tc : {32, 16}) {
+    const size_t lds = (size_t)tc * (g.ldm + g.ldx) * es;
+    if (lds <= (size_t)gram_max_lds_bytes()) {
+      g.tc = tc;
+      g.lds_bytes = lds;
+      break;
+    }
+  }
+  if (g.tc == 0) return false;
+  g.nColTiles = (m.C + g.tc - 1) / g.tc;
+  int64_t ns = std::max<int64_t>(1, kTargetGramWGs / g.nGroups);
+  ns = std::min<int64_t>(ns, g.nColTiles);
+  g.colTilesPerSplit = (g.nColTiles + ns - 1) / ns;
+  g.nSplit = (int32_t)((g.nColTiles + g.colTilesPerSplit - 1) / g.colTilesPerSplit);
+  return true;
+}
+
+// carve (or measure, base == nullptr) the workspace; returns bytes
+size_t carve(fctn_plan_s* P, char* base) {
+  Carver c{base, 0};
+  const int N = P->N;
+  const size_t es = P->es;
+  const size_t acc_es = P->prec == FCTN_F64 ? 8 : 4;
+  P->X = c.take(P->numel * es);
+  P->Z = c.take(P->numel * es);
+  P->bits = (uint32_t*)c.take(((P->numel + 63) / 64) * 2 * sizeof(uint32_t));
+  P->bad_nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (P->numel + 255) / 256));
+  P->bad_part = (int32_t*)c.take(P->bad_nblk * sizeof(int32_t));
+  int64_t smax = 1, imax = 1;
+  P->max_cls = 1;
+  size_t part_bytes = 0;
+  for (int k = 0; k < N; ++k) {
+    const ModeInfo& m = P->mode[k];
+    P->A64[k] = (double*)c.take(P->fnum[k] * sizeof(double));
+    P->Aw[k] = c.take(P->fnum[k] * es);
+    P->Au[k] = c.take(P->fnum[k] * es);
+    P->Q[k] = (double*)c.take(m.Ik * m.Ik * sizeof(double));
+    P->lamcol[k] = (double*)c.take(m.Ik * sizeof(double));
+    smax = std::max(smax, m.s);
+    imax = std::max(imax, m.Ik);
+    P->max_cls = std::max(P->max_cls, m.ncls);
+    part_bytes = std::max(part_bytes, (size_t)m.geom.nSplit * m.geom.nTiles * 256 * acc_es);
+  }
+  for (int p = 0; p < 2; ++p) P->P[p] = (N == 4) ? c.take(P->pnum[p] * es) : nullptr;
+  P->part = c.take(part_bytes);
+  P->G = (double*)c.take(smax * smax * sizeof(double));
+  P->B = (double*)c.take(imax * smax * sizeof(double));
+  P->At = (double*)c.take(imax * smax * sizeof(double));
+  P->trace_part = (double*)c.take((size_t)N * P->max_cls * sizeof(double));
+  P->lam_half = (double*)c.take(N * sizeof(double));
+  P->ncls_dev = (int32_t*)c.take(N * sizeof(int32_t));
+  P->xpart = (double*)c.take(kXBlocks * 3 * sizeof(double));
+  P->hist = (double*)c.take(kHist * 4 * sizeof(double));
+  P->scratch_slot = (double*)c.take(4 * sizeof(double));
+  return align256(c.off);
+}
+
+bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
+  memset(P, 0, sizeof(*P));
+  P->d = *d;
+  P->N = d->order;
+  P->prec = d->precision;
+  P->es = P->prec == FCTN_F64 ? 8 : 4;
+  P->numel = 1;
+  for (int k = 0; k < P->N; ++k) {
+    P->dims[k] = d->dims[k];
+    P->numel *= d->dims[k];
+  }
+  fill_ranks(d, P->R);
+  for (int k = 0; k < P->N; ++k) {
+    int64_t n = 1;
+    for (int j = 0; j < P->N; ++j) n *= (j == k) ? P->dims[k] : P->R[k][j];
+    P->fnum[k] = n;
+  }
+  setup_modes(P);
+  for (int k = 0; k < P->N; ++k) {
+    if (!solve_supported((int32_t)P->mode[k].s)) return false;
+    if (!setup_geom(P->mode[k], P->es)) return false;
+  }
+  return true;
+}
+
+const void* src_ptr(fctn_plan_s* P, int src) {
+  if (src == SRC_P12) return P->P[0];
+  if (src == SRC_P34) return P->P[1];
+  return P->Aw[src - SRC_F0];
+}
+
+#define FCTN_LAUNCH(P, expr)                                  \
+  do {                                                        \
+    hipError_t e_ = (expr);                                   \
+    if (e_ == hipSuccess && (P)->debug) e_ = hipStreamSynchronize((P)->st); \
+    if (e_ != hipSuccess) {                                   \
+      (P)->sticky = FCTN_E_DEVICE;                            \
+      return FCTN_E_DEVICE;                                   \
+    }                                                         \
+  } while (0)
+
+// pair p is built from factors (0,1) for p = 0 and (2,3) for p = 1
+fctn_status ensure_pair(fctn_plan_s* P, int p, bool force) {
+  const int fa = p == 0 ? 0 : 2, fb = fa + 1;
+  if (!force && P->pvalid[p] && P->pver[p][0] == P->fver[fa] && P->pver[p][1] == P->fver[fb])
+    return FCTN_OK;
+  PairDesc pd = P->pd[p];
+  pd.Fa = P->Aw[fa];
+  pd.Fb = P->Aw[fb];
+  FCTN_LAUNCH(P, launch_pair(P->prec, pd, P->P[p], P->st));
+  P->pvalid[p] = true;
+  P->pver[p][0] = P->fver[fa];
+  P->pver[p][1] = P->fver[fb];
+  return FCTN_OK;
+}
+
+int pair_of_mode(int N, int k) {
+  if (N != 4) return -1;
+  return (k <= 1) ? 1 : 0;
+}
+
+fctn_status prepare_mode(fctn_plan_s* P, int k) {
+  const int p = pair_of_mode(P->N, k);
+  if (p >= 0) return ensure_pair(P, p, P->d.reuse == 0);
+  return FCTN_OK;
+}
+
+MGen resolved_mgen(fctn_plan_s* P, int k) {
+  MGen g = P->mode[k].mg;
+  g.U = src_ptr(P, P->mode[k].u_src);
+  g.V = src_ptr(P, P->mode[k].v_src);
+  return g;
+}
+
+fctn_status gram_rhs(fctn_plan_s* P, int k, double* G, double* B) {
+  fctn_status s = prepare_mode(P, k);
+  if (s != FCTN_OK) return s;
+  const ModeInfo& m = P->mode[k];
+  const MGen g = resolved_mgen(P, k);
+  FCTN_LAUNCH(P, launch_gram_rhs(P->prec, g, P->X, m.xv, m.geom, P->part, P->st));
+  FCTN_LAUNCH(P, launch_reduce_gb(P->prec, m.geom, P->part, P->A64[k], m.spost, P->d.rho, G, B,
+                                  P->st));
+  return FCTN_OK;
+}
+
+fctn_status solve(fctn_plan_s* P, int k, const double* G, const double* B) {
+  const ModeInfo& m = P->mode[k];
+  FCTN_LAUNCH(P, launch_solve_classes(G, B, P->Q[k], (int32_t)m.Ik, (int32_t)m.s,
+                                      P->d.lambda[k], P->d.delta[k], P->d.rho, P->At,
+                                      P->trace_part + (size_t)k * P->max_cls, P->st));
+  FCTN_LAUNCH(P, launch_backtransform(P->prec, P->Q[k], P->At, (int32_t)m.Ik, (int32_t)m.s,
+                                      m.spost, P->A64[k], P->Aw[k], P->Au[k], P->st));
+  P->fver[k]++;
+  return FCTN_OK;
+}
+
+fctn_status reconstruct(fctn_plan_s* P, int k, void* Z) {
+  const int p = pair_of_mode(P->N, k);
+  if (p >= 0) {
+    fctn_status s = ensure_pair(P, p, P->d.reuse == 0);
+    if (s != FCTN_OK) return s;
+  }
+  const ModeInfo& m = P->mode[k];
+  const MGen g = resolved_mgen(P, k);
+  FCTN_LAUNCH(P, launch_reconstruct(P->prec, g, P->Au[k], Z, m.xv, (int32_t)m.s, m.C, P->st));
+  return FCTN_OK;
+}
+
+fctn_status x_update(fctn_plan_s* P, const void* Z, double* slot, bool with_trace) {
+  FCTN_LAUNCH(P, launch_x_update(P->prec, P->X, Z, P->bits, P->d.rho, P->numel, kXBlocks,
+                                 P->xpart, P->st));
+  FCTN_LAUNCH(P, launch_stats(P->xpart, kXBlocks, P->trace_part, P->lam_half, P->ncls_dev,
+                              with_trace ? P->N : 0, P->max_cls, slot, P->st));
+  return FCTN_OK;
+}
+
+void sweep_order(const fctn_plan_s* P, int64_t t, int* order) {
+  for (int k = 0; k < P->N; ++k) order[k] = k;
+  if (P->d.order_policy == 1 && P->N == 4 && (t % 2) == 1) {
+    order[0] = 2; order[1] = 3; order[2] = 0; order[3] = 1;
+  }
+}
+
+fctn_status one_sweep(fctn_plan_s* P) {
+  int order[FCTN_MAX_ORDER];
+  sweep_order(P, P->sweeps_done, order);
+  fctn_status s;
+  for (int n = 0; n < P->N; ++n) {
+    const int k = order[n];
+    if ((s = gram_rhs(P, k, P->G, P->B)) != FCTN_OK) return s;
+    if ((s = solve(P, k, P->G, P->B)) != FCTN_OK) return s;
+  }
+  const int last = order[P->N - 1];
+  if ((s = reconstruct(P, last, P->Z)) != FCTN_OK) return s;
+  if ((s = x_update(P, P->Z, P->hist + (P->sweeps_done % kHist) * 4, true)) != FCTN_OK) return s;
+  P->sweeps_done++;
+  return FCTN_OK;
+}
+
+fctn_status read_slot(fctn_plan_s* P, const double* slot, fctn_sweep_stats* out) {
+  double h[4];
+  if (hipMemcpyAsync(h, slot, sizeof(h), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+      hipStreamSynchronize(P->st) != hipSuccess) {
+    P->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  out->rel_change = h[0];
+  out->f_data = h[1];
+  out->f_trace = h[2];
+  out->objective = h[3];
+  return FCTN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fctn_workspace_bytes(const fctn_desc* desc) {
+  if (validate(desc) != FCTN_OK) return 0;
+  fctn_plan_s* P = new (std::nothrow) fctn_plan_s;
+  if (!P) return 0;
+  size_t bytes = 0;
+  if (init_plan_struct(desc, P)) bytes = carve(P, nullptr);
+  delete P;
+  return bytes;
+}
+
+fctn_status fctn_mode_sizes(const fctn_desc* desc, int32_t k, int64_t* s_k, int64_t* I_k) {
+  fctn_status v = validate(desc);
+  if (v != FCTN_OK) return v;
+  if (k < 0 || k >= desc->order || !s_k || !I_k) return FCTN_E_INVALID;
+  int R[FCTN_MAX_ORDER][FCTN_MAX_ORDER];
+  fill_ranks(desc, R);
+  int64_t s = 1;
+  for (int j = 0; j < desc->order; ++j)
+    if (j != k) s *= R[k][j];
+  *s_k = s;
+  *I_k = desc->dims[k];
+  return FCTN_OK;
+}
+
+fctn_status fctn_plan(const fctn_desc* desc, void* ws_dev, size_t ws_bytes, void* hip_stream,
+                      fctn_plan_t* out) {
+  if (!out) return FCTN_E_INVALID;
+  *out = nullptr;
+  fctn_status v = validate(desc);
+  if (v != FCTN_OK) return v;
+  if (!ws_dev || ((uintptr_t)ws_dev & 255)) return FCTN_E_INVALID;
+  fctn_plan_s* P = new (std::nothrow) fctn_plan_s;
+  if (!P) return FCTN_E_NOMEM;
+  if (!init_plan_struct(desc, P)) {
+    delete P;
+    return FCTN_E_UNSUPPORTED;
+  }
+  const size_t need = carve(P, nullptr);
+  if (ws_bytes < need) {
+    delete P;
+    return FCTN_E_NOMEM;
+  }
+  carve(P, (char*)ws_dev);
+  P->st = (hipStream_t)hip_stream;
+  const char* dbg = getenv("FCTN_DEBUG");
+  P->debug = dbg && dbg[0] == '1';
+  // zero state, bases, per-mode constants
+  bool ok = hipMemsetAsync(ws_dev, 0, need, P->st) == hipSuccess;
+  std::vector<double> lh(P->N);
+  std::vector<int32_t> nc(P->N);
+  for (int k = 0; k < P->N && ok; ++k) {
+    ok = launch_build_basis(P->Q[k], P->lamcol[k], (int32_t)P->mode[k].Ik, desc->delta[k],
+                            P->st) == hipSuccess;
+    lh[k] = 0.5 * desc->lambda[k];
+    nc[k] = P->mode[k].ncls;
+  }
+  ok = ok && hipMemcpyAsync(P->lam_half, lh.data(), P->N * sizeof(double),
+                            hipMemcpyHostToDevice, P->st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(P->ncls_dev, nc.data(), P->N * sizeof(int32_t),
+                            hipMemcpyHostToDevice, P->st) == hipSuccess;
+  ok = ok && hipStreamSynchronize(P->st) == hipSuccess;
+  if (!ok) {
+    delete P;
+    return FCTN_E_DEVICE;
+  }
+  *out = P;
+  return FCTN_OK;
+}
+
+fctn_status fctn_set_factors(fctn_plan_t P, const double* const* A_host) {
+  if (!P || !A_host) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  for (int k = 0; k < P->N; ++k)
+    if (!A_host[k]) return FCTN_E_INVALID;
+  for (int k = 0; k < P->N; ++k) {
+    if (hipMemcpyAsync(P->A64[k], A_host[k], P->fnum[k] * sizeof(double), hipMemcpyHostToDevice,
+                       P->st) != hipSuccess) {
+      P->sticky = FCTN_E_DEVICE;
+      return FCTN_E_DEVICE;
+    }
+    const ModeInfo& m = P->mode[k];
+    FCTN_LAUNCH(P, launch_cast_factor(P->prec, P->A64[k], P->Aw[k], P->Au[k], (int32_t)m.Ik,
+                                      (int32_t)m.s, m.spost, P->st));
+    P->fver[k]++;
+  }
+  if (hipStreamSynchronize(P->st) != hipSuccess) {
+    P->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  P->pvalid[0] = P->pvalid[1] = false;
+  return FCTN_OK;
+}
+
+fctn_status fctn_set_observed(fctn_plan_t P, const void* Y_dev, const uint8_t* mask_dev) {
+  if (!P || !Y_dev || !mask_dev) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  FCTN_LAUNCH(P, launch_init_observed(P->prec, Y_dev, mask_dev, P->X, P->bits, P->bad_part,
+                                      P->numel, P->bad_nblk, P->st));
+  std::vector<int32_t> bad(P->bad_nblk);
+  if (hipMemcpyAsync(bad.data(), P->bad_part, bad.size() * sizeof(int32_t),
+                     hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+      hipStreamSynchronize(P->st) != hipSuccess) {
+    P->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  for (int32_t b : bad)
+    if (b) return FCTN_E_NUMERIC;
+  return FCTN_OK;
+}
+
+fctn_status fctn_set_x(fctn_plan_t P, const void* X_dev) {
+  if (!P || !X_dev) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  if (hipMemcpyAsync(P->X, X_dev, P->numel * P->es, hipMemcpyDeviceToDevice, P->st) !=
+      hipSuccess) {
+    P->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  return FCTN_OK;
+}
+
+fctn_status fctn_sweep(fctn_plan_t P, int32_t nsweeps, fctn_sweep_stats* stats_host) {
+  if (!P || nsweeps < 0) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  for (int32_t i = 0; i < nsweeps; ++i) {
+    fctn_status s = one_sweep(P);
+    if (s != FCTN_OK) return s;
+  }
+  if (stats_host) {
+    if (P->sweeps_done == 0) {
+      memset(stats_host, 0, sizeof(*stats_host));
+      return FCTN_OK;
+    }
+    return read_slot(P, P->hist + ((P->sweeps_done - 1) % kHist) * 4, stats_host);
+  }
+  return FCTN_OK;
+}
+
+fctn_status fctn_sweep_many(fctn_plan_t* plans, int32_t count, int32_t nsweeps) {
+  if (!plans || count < 0 || nsweeps < 0) return FCTN_E_INVALID;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!plans[i]) return FCTN_E_INVALID;
+    if (plans[i]->sticky != FCTN_OK) return plans[i]->sticky;
+  }
+  // round-robin one sweep per plan so that work queued on distinct streams overlaps
+  for (int32_t t = 0; t < nsweeps; ++t)
+    for (int32_t i = 0; i < count; ++i) {
+      fctn_status s = one_sweep(plans[i]);
+      if (s != FCTN_OK) return s;
+    }
+  return FCTN_OK;
+}
+
+fctn_status fctn_complete(fctn_plan_t P, int32_t max_sweeps, double tol, int32_t check_every,
+                          void* X_out_dev, fctn_stats* stats_host) {
+  if (!P || max_sweeps < 0 || check_every < 1) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  int32_t done = 0;
+  fctn_sweep_stats last{};
+  bool have_last = false;
+  while (done < max_sweeps) {
+    const int32_t n = std::min(check_every, max_sweeps - done);
+    for (int32_t i = 0; i < n; ++i) {
+      fctn_status s = one_sweep(P);
+      if (s != FCTN_OK) return s;
+    }
+    done += n;
+    if (tol > 0.0) {
+      fctn_status s = read_slot(P, P->hist + ((P->sweeps_done - 1) % kHist) * 4, &last);
+      if (s != FCTN_OK) return s;
+      have_last = true;
+      if (last.rel_change <= tol) break;
+    }
+  }
+  if (X_out_dev) {
+    if (hipMemcpyAsync(X_out_dev, P->X, P->numel * P->es, hipMemcpyDeviceToDevice, P->st) !=
+        hipSuccess) {
+      P->sticky = FCTN_E_DEVICE;
+      return FCTN_E_DEVICE;
+    }
+  }
+  if (stats_host) {
+    stats_host->sweeps_done = done;
+    if (done > 0 && !have_last) {
+      fctn_status s = read_slot(P, P->hist + ((P->sweeps_done - 1) % kHist) * 4, &last);
+      if (s != FCTN_OK) return s;
+    }
+    stats_host->rel_change = done > 0 ? last.rel_change : 0.0;
+    stats_host->objective = done > 0 ? last.objective : 0.0;
+  }
+  return FCTN_OK;
+}
+
+fctn_status fctn_get_history(fctn_plan_t P, int32_t first, int32_t count,
+                             fctn_sweep_stats* out_host) {
+  if (!P || !out_host || first < 0 || count < 0) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  if ((int64_t)first + count > P->sweeps_done || P->sweeps_done - first > kHist)
+    return FCTN_E_INVALID;
+  std::vector<double> h((size_t)kHist * 4);
+  if (hipMemcpyAsync(h.data(), P->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                     P->st) != hipSuccess ||
+      hipStreamSynchronize(P->st) != hipSuccess) {
+    P->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    const double* e = &h[((first + i) % kHist) * 4];
+    out_host[i].rel_change = e[0];
+    out_host[i].f_data = e[1];
+    out_host[i].f_trace = e[2];
+    out_host[i].objective = e[3];
+  }
+  return FCTN_OK;
+}
+
+fctn_status fctn_get_x(fctn_plan_t P, void* dst_dev) {
+  if (!P || !dst_dev) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  if (hipMemcpyAsync(dst_dev, P->X, P->numel * P->es, hipMemcpyDeviceToDevice, P->st) !=
+      hipSuccess) {
+    P->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  return FCTN_OK;
+}
+
+fctn_status fctn_get_factor(fctn_plan_t P, int32_t k, double* dst_dev) {
+  if (!P || !dst_dev || k < 0 || k >= P->N) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  if (hipMemcpyAsync(dst_dev, P->A64[k], P->fnum[k] * sizeof(double), hipMemcpyDeviceToDevice,
+                     P->st) != hipSuccess) {
+    P->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  return FCTN_OK;
+}
+
+fctn_status fctn_step_gram_rhs(fctn_plan_t P, int32_t k, double* G_dev, double* B_dev) {
+  if (!P || !G_dev || !B_dev || k < 0 || k >= P->N) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  return gram_rhs(P, k, G_dev, B_dev);
+}
+
+fctn_status fctn_step_solve(fctn_plan_t P, int32_t k, const double* G_dev, const double* B_dev,
+                            double* trace_host) {
+  if (!P || !G_dev || !B_dev || k < 0 || k >= P->N) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  fctn_status s = solve(P, k, G_dev, B_dev);
+  if (s != FCTN_OK) return s;
+  if (trace_host) {
+    const int nc = P->mode[k].ncls;
+    std::vector<double> tp(nc);
+    if (hipMemcpyAsync(tp.data(), P->trace_part + (size_t)k * P->max_cls, nc * sizeof(double),
+                       hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+        hipStreamSynchronize(P->st) != hipSuccess) {
+      P->sticky = FCTN_E_DEVICE;
+      return FCTN_E_DEVICE;
+    }
+    double t = 0.0;
+    for (double v : tp) t += v;
+    *trace_host = t;
+  }
+  return FCTN_OK;
+}
+
+fctn_status fctn_step_reconstruct(fctn_plan_t P, int32_t k, void* Z_dev) {
+  if (!P || !Z_dev || k < 0 || k >= P->N) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  return reconstruct(P, k, Z_dev);
+}
+
+fctn_status fctn_step_x_update(fctn_plan_t P, const void* Z_dev, fctn_sweep_stats* stats_host) {
+  if (!P || !Z_dev || ((uintptr_t)Z_dev & 15)) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  // the trace term is not part of this step's scalars
+  fctn_status s = x_update(P, Z_dev, P->scratch_slot, false);
+  if (s != FCTN_OK) return s;
+  if (stats_host) return read_slot(P, P->scratch_slot, stats_host);
+  return FCTN_OK;
+}
+
+fctn_status fctn_destroy(fctn_plan_t P) {
+  if (!P) return FCTN_E_INVALID;
+  hipStreamSynchronize(P->st);
+  delete P;
+  return FCTN_OK;
+}
+
+const char* fctn_status_str(fctn_status s) {
+  switch (s) {
+    case FCTN_OK: return "ok";
+    case FCTN_E_INVALID: return "invalid argument";
+    case FCTN_E_NOMEM: return "workspace too small";
+    case FCTN_E_DEVICE: return "HIP runtime error";
+    case FCTN_E_NUMERIC: return "non-finite observed value";
+    case FCTN_E_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,276 @@
+// Elementwise and bookkeeping kernels: observed-data setup (Algorithm 1
+// initialization), factor casts, the Fourier eigenbasis of L_k (eq. 7),
+// the cached pair tensors of the reuse mechanism (Section 3.3), the X update
+// of eq. 10 with its norm partials, and the per-sweep scalars.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace fctn {
+
+// ---------------------------------------------------------------------------
+// X <- P_Omega(Y); Omega packed to one bit per element; non-finite observed
+// values flagged per block.  One wave handles 64 consecutive elements per
+// step so that its ballot is exactly two mask words.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) init_observed_k(const T* __restrict__ Y,
+                                                       const uint8_t* __restrict__ mask,
+                                                       T* __restrict__ X, uint32_t* __restrict__ bits,
+                                                       int32_t* __restrict__ bad_part, int64_t n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  int bad = 0;
+  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+    const int64_t i = base + lane;
+    bool obs = false;
+    if (i < n) {
+      obs = mask[i] != 0;
+      T y = T(0);
+      if (obs) {
+        y = Y[i];
+        if (!isfinite(y)) bad = 1;
+      }
+      X[i] = y;
+    }
+    const uint64_t b = __ballot(obs);
+    if (lane == 0) bits[base >> 5] = (uint32_t)b;
+    if (lane == 1) bits[(base >> 5) + 1] = (uint32_t)(b >> 32);
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) bad_part[blockIdx.x] = bad;
+}
+
+hipError_t launch_init_observed(int prec, const void* Y, const uint8_t* mask, void* X,
+                                uint32_t* bits, int32_t* bad_part, int64_t n, int nblk,
+                                hipStream_t st) {
+  if (prec == P_F64)
+    init_observed_k<double><<<nblk, 256, 0, st>>>((const double*)Y, mask, (double*)X, bits,
+                                                   bad_part, n);
+  else
+    init_observed_k<float><<<nblk, 256, 0, st>>>((const float*)Y, mask, (float*)X, bits,
+                                                  bad_part, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// working-precision copies of a float64 factor (round to nearest even): Aw in
+// the factor layout and Au as the row-major mode-k unfolding (I_k x s_k)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void cast_k(const double* __restrict__ a, T* __restrict__ w, T* __restrict__ u,
+                       int32_t Ik, int32_t s, int64_t spost) {
+  const int64_t n = (int64_t)Ik * s;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    w[e] = (T)a[e];
+    const int i = (int)(e / s), j = (int)(e % s);
+    u[e] = (T)a[(j / spost) * ((int64_t)Ik * spost) + (int64_t)i * spost + j % spost];
+  }
+}
+
+hipError_t launch_cast_factor(int prec, const double* A64, void* Aw, void* Au, int32_t Ik,
+                              int32_t s, int64_t spost, hipStream_t st) {
+  const int64_t n = (int64_t)Ik * s;
+  const int nb = (int)(cdiv(n, 256) < 1024 ? cdiv(n, 256) : 1024);
+  if (n == 0) return hipSuccess;
+  if (prec == P_F64)
+    cast_k<double><<<nb, 256, 0, st>>>(A64, (double*)Aw, (double*)Au, Ik, s, spost);
+  else
+    cast_k<float><<<nb, 256, 0, st>>>(A64, (float*)Aw, (float*)Au, Ik, s, spost);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Real orthonormal eigenbasis of the circulant L = (2 + delta) I - S - S^T:
+// column 0 is constant; columns 2c-1, 2c are the cosine and sine of frequency
+// c (1 <= c < n/2); for even n the last column alternates in sign.  Column
+// eigenvalue: delta + 4 sin^2(pi c / n).  Q is n x n row-major (Q[i][col]).
+// ---------------------------------------------------------------------------
+__global__ void basis_k(double* __restrict__ Q, double* __restrict__ lam_col, int32_t n,
+                        double delta) {
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), col = (int)(e % n);
+    double v;
+    int c;
+    if (col == 0) {
+      c = 0;
+      v = 1.0 / sqrt((double)n);
+    } else if ((n % 2 == 0) && col == n - 1) {
+      c = n / 2;
+      v = ((i & 1) ? -1.0 : 1.0) / sqrt((double)n);
+    } else {
+      c = (col + 1) / 2;
+      const int64_t m = ((int64_t)i * c) % n;
+      const double ang = 2.0 * (double)m / (double)n;   // angle / pi
+      v = sqrt(2.0 / n) * ((col & 1) ? cospi(ang) : sinpi(ang));
+    }
+    Q[e] = v;
+    if (i == 0) {
+      const double sn = sinpi((double)c / (double)n);
+      lam_col[col] = delta + 4.0 * sn * sn;
+    }
+  }
+}
+
+hipError_t launch_build_basis(double* Q, double* lam_col, int32_t n, double delta,
+                              hipStream_t st) {
+  const int64_t nn = (int64_t)n * n;
+  const int nb = (int)(cdiv(nn, 256) < 1024 ? cdiv(nn, 256) : 1024);
+  basis_k<<<nb, 256, 0, st>>>(Q, lam_col, n, delta);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Pair tensor of the reuse mechanism (two factors contracted over their
+// shared bond), written in the layout the sub-network generator reads.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) pair_k(PairDesc pd, T* __restrict__ P, int64_t total) {
+  const T* Fa = (const T*)pd.Fa;
+  const T* Fb = (const T*)pd.Fb;
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    int64_t q = o;
+    const int b2 = (int)(q % pd.n2b); q /= pd.n2b;
+    const int a2 = (int)(q % pd.n2a); q /= pd.n2a;
+    const int b1 = (int)(q % pd.n1b); q /= pd.n1b;
+    const int a1 = (int)(q % pd.n1a); q /= pd.n1a;
+    const int ib = (int)(q % pd.Ib);
+    const int ia = (int)(q / pd.Ib);
+    const T* pa = Fa + ia * pd.a_i + a1 * pd.a_1 + a2 * pd.a_2;
+    const T* pb = Fb + ib * pd.b_i + b1 * pd.b_1 + b2 * pd.b_2;
+    T acc = T(0);
+    for (int k = 0; k < pd.K; ++k) acc += pa[k * pd.a_k] * pb[k * pd.b_k];
+    P[o] = acc;
+  }
+}
+
+hipError_t launch_pair(int prec, const PairDesc& pd, void* P, hipStream_t st) {
+  const int64_t total = (int64_t)pd.Ia * pd.Ib * pd.n1a * pd.n1b * pd.n2a * pd.n2b;
+  const int nb = (int)(cdiv(total, 256) < 4096 ? cdiv(total, 256) : 4096);
+  if (prec == P_F64)
+    pair_k<double><<<nb, 256, 0, st>>>(pd, (double*)P, total);
+  else
+    pair_k<float><<<nb, 256, 0, st>>>(pd, (float*)P, total);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// eq. 10 as a select: X on Omega already equals Y, so only X, Z and the mask
+// bits are read.  Per-block float64 partials: ||X+ - X||^2, ||X||^2,
+// ||X+ - Z||^2.  16-byte vector accesses; a fixed grid keeps the partial
+// sums (and so the scalars) deterministic.
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec;
+template <> struct Vec<float> { typedef float4 t; static constexpr int w = 4; };
+template <> struct Vec<double> { typedef double2 t; static constexpr int w = 2; };
+
+template <typename T>
+__device__ inline void xupd_one(T& x, T z, bool obs, T rho, T opr, double& sdx, double& sxx,
+                                double& sdz) {
+  const T xn = obs ? x : (z + rho * x) / opr;
+  const double d = (double)xn - (double)x;
+  const double e = (double)xn - (double)z;
+  sdx += d * d;
+  sxx += (double)x * (double)x;
+  sdz += e * e;
+  x = xn;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) x_update_k(T* __restrict__ X, const T* __restrict__ Z,
+                                                  const uint32_t* __restrict__ bits, double rho_d,
+                                                  int64_t n, double* __restrict__ xpart) {
+  typedef typename Vec<T>::t V;
+  constexpr int W = Vec<T>::w;
+  const T rho = (T)rho_d, opr = (T)(1.0 + rho_d);
+  double sdx = 0.0, sxx = 0.0, sdz = 0.0;
+  const int64_t nv = n / W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride) {
+    V xv = ((const V*)X)[v];
+    const V zv = ((const V*)Z)[v];
+    const int64_t i0 = v * W;
+    const uint32_t word = bits[i0 >> 5] >> (i0 & 31);
+    T* xs = (T*)&xv;
+    const T* zs = (const T*)&zv;
+#pragma unroll
+    for (int j = 0; j < W; ++j) xupd_one<T>(xs[j], zs[j], (word >> j) & 1u, rho, opr, sdx, sxx, sdz);
+    ((V*)X)[v] = xv;
+  }
+  for (int64_t i = nv * W + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    T x = X[i];
+    xupd_one<T>(x, Z[i], (bits[i >> 5] >> (i & 31)) & 1u, rho, opr, sdx, sxx, sdz);
+    X[i] = x;
+  }
+  __shared__ double red[3][4];
+  sdx = wave_sum(sdx);
+  sxx = wave_sum(sxx);
+  sdz = wave_sum(sdz);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = sdx;
+    red[1][w] = sxx;
+    red[2][w] = sdz;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double s = 0.0;
+    for (int k = 0; k < 4; ++k) s += red[threadIdx.x][k];
+    xpart[blockIdx.x * 3 + threadIdx.x] = s;
+  }
+}
+
+hipError_t launch_x_update(int prec, void* X, const void* Z, const uint32_t* bits, double rho,
+                           int64_t n, int nblk, double* xpart, hipStream_t st) {
+  if (prec == P_F64)
+    x_update_k<double><<<nblk, 256, 0, st>>>((double*)X, (const double*)Z, bits, rho, n, xpart);
+  else
+    x_update_k<float><<<nblk, 256, 0, st>>>((float*)X, (const float*)Z, bits, rho, n, xpart);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-sweep scalars: rel_change, f_data, f_trace, objective (fixed order)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) stats_k(const double* __restrict__ xpart, int nblk,
+                                               const double* __restrict__ trace_part,
+                                               const double* __restrict__ lam_half,
+                                               const int32_t* __restrict__ ncls, int N,
+                                               int max_cls, double* __restrict__ slot) {
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += 256)
+    for (int q = 0; q < 3; ++q) s[q] += xpart[b * 3 + q];
+  __shared__ double red[3][4];
+  for (int q = 0; q < 3; ++q) {
+    const double v = wave_sum(s[q]);
+    if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[3];
+    for (int q = 0; q < 3; ++q) t[q] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
+    double ftr = 0.0;
+    for (int k = 0; k < N; ++k) {
+      double tk = 0.0;
+      for (int c = 0; c < ncls[k]; ++c) tk += trace_part[k * max_cls + c];
+      ftr += lam_half[k] * tk;
+    }
+    slot[0] = sqrt(t[0]) / sqrt(t[1]);
+    slot[1] = 0.5 * t[2];
+    slot[2] = ftr;
+    slot[3] = 0.5 * t[2] + ftr;
+  }
+}
+
+hipError_t launch_stats(const double* xpart, int nblk, const double* trace_part,
+                        const double* lam_half, const int32_t* ncls, int N, int max_cls,
+                        double* hist_slot, hipStream_t st) {
+  stats_k<<<1, 256, 0, st>>>(xpart, nblk, trace_part, lam_half, ncls, N, max_cls, hist_slot);
+  return hipGetLastError();
+}
+
+}  // namespace fctn

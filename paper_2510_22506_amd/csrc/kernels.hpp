@@ -1,0 +1,80 @@
+// Internal launch interface of the FCTN kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fctn {
+
+// Sub-network generator (Property 1 with the reuse mechanism's operands):
+//   M[ru * Rv + rv, cu * Cv + cv] = sum_kap U[ru, cu, kap] * V[rv, cv, kap]
+// U, V are strided views of a factor tensor or of a cached pair tensor.
+struct MGen {
+  const void* U;
+  int64_t u_ru, u_cu, u_k;
+  const void* V;
+  int64_t v_rv, v_cv, v_k;
+  int32_t Ru, Rv, K;
+  int64_t Cu, Cv;
+};
+
+// X_(k)[ik, cu * Cv + cv] = X[cu * x_cu + cv * x_cv + ik * x_ik]
+struct XView {
+  int64_t x_cu, x_cv, x_ik;
+  int32_t Ik;
+};
+
+// Launch geometry of the fused sub-network / Gram / right-hand-side pass.
+struct GramGeom {
+  int32_t s, sp, Ik, ip;     // sizes and 16-padded sizes
+  int32_t nG, nB, nTiles;    // upper-triangle Gram tiles, RHS tiles, total
+  int32_t nbj;               // 16-blocks along s
+  int32_t tilesPerGroup, nGroups;
+  int32_t tc;                // columns per LDS tile
+  int64_t nColTiles, colTilesPerSplit;
+  int32_t nSplit;
+  int32_t ldm, ldx, xrows;   // LDS leading dims and X rows held per group
+  size_t lds_bytes;
+};
+
+// pair tensor P[(ia, ib)][(a1, b1)][(a2, b2)] = sum_kap Fa[ia, a1, a2, kap] Fb[ib, b1, b2, kap]
+struct PairDesc {
+  const void* Fa;
+  int64_t a_i, a_1, a_2, a_k;
+  const void* Fb;
+  int64_t b_i, b_1, b_2, b_k;
+  int32_t Ia, Ib, n1a, n2a, n1b, n2b, K;
+};
+
+// precision codes shared with the C ABI
+enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
+
+hipError_t launch_init_observed(int prec, const void* Y, const uint8_t* mask, void* X,
+                                uint32_t* bits, int32_t* bad_part, int64_t n, int nblk,
+                                hipStream_t st);
+hipError_t launch_cast_factor(int prec, const double* A64, void* Aw, void* Au, int32_t Ik,
+                              int32_t s, int64_t spost, hipStream_t st);
+hipError_t launch_build_basis(double* Q, double* lam_col, int32_t n, double delta, hipStream_t st);
+hipError_t launch_pair(int prec, const PairDesc& pd, void* P, hipStream_t st);
+hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView& xv,
+                           const GramGeom& g, void* part, hipStream_t st);
+hipError_t launch_reduce_gb(int prec, const GramGeom& g, const void* part, const double* A64,
+                            int64_t spost, double rho, double* G, double* B, hipStream_t st);
+hipError_t launch_solve_classes(const double* G, const double* B, const double* Q,
+                                int32_t Ik, int32_t s, double lam, double delta, double rho,
+                                double* At, double* trace_part, hipStream_t st);
+hipError_t launch_backtransform(int prec, const double* Q, const double* At, int32_t Ik,
+                                int32_t s, int64_t spost, double* A64, void* Aw, void* Au,
+                                hipStream_t st);
+hipError_t launch_reconstruct(int prec, const MGen& mg, const void* Au, void* Z,
+                              const XView& xv, int32_t s, int64_t C, hipStream_t st);
+hipError_t launch_x_update(int prec, void* X, const void* Z, const uint32_t* bits, double rho,
+                           int64_t n, int nblk, double* xpart, hipStream_t st);
+hipError_t launch_stats(const double* xpart, int nblk, const double* trace_part,
+                        const double* lam_half, const int32_t* ncls, int N, int max_cls,
+                        double* hist_slot, hipStream_t st);
+
+int gram_max_lds_bytes();
+int solve_supported(int32_t s);
+
+}  // namespace fctn

@@ -1,0 +1,303 @@
+"""ctypes binding of libfctn.so (argument marshalling only).
+
+Every function of the C ABI (include/fctn.h) is exposed under its own name;
+``Plan`` wraps a plan whose workspace, inputs and outputs are torch tensors on
+the GPU and whose stream is a torch stream.  All arithmetic runs in the HIP
+kernels of libfctn.so; there is no fallback: if the library is missing the
+first call raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfctn.so")
+
+FCTN_MAX_ORDER = 8
+FCTN_MAX_BONDS = 28
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = range(6)
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
+
+
+class FctnError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {fctn_status_str(status)} (status {status})")
+
+
+class fctn_desc(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int32),
+        ("dims", ctypes.c_int64 * FCTN_MAX_ORDER),
+        ("ranks", ctypes.c_int32 * FCTN_MAX_BONDS),
+        ("lambda_", ctypes.c_double * FCTN_MAX_ORDER),
+        ("delta", ctypes.c_double * FCTN_MAX_ORDER),
+        ("rho", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("reuse", ctypes.c_int32),
+        ("order_policy", ctypes.c_int32),
+    ]
+
+
+class fctn_sweep_stats(ctypes.Structure):
+    _fields_ = [("rel_change", ctypes.c_double), ("f_data", ctypes.c_double),
+                ("f_trace", ctypes.c_double), ("objective", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class fctn_stats(ctypes.Structure):
+    _fields_ = [("sweeps_done", ctypes.c_int32), ("rel_change", ctypes.c_double),
+                ("objective", ctypes.c_double)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(fctn_desc)
+_SIGS = {
+    "fctn_workspace_bytes": (ctypes.c_size_t, [_D]),
+    "fctn_plan": (ctypes.c_int, [_D, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "fctn_set_factors": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]),
+    "fctn_set_observed": (ctypes.c_int, [_P, _P, _P]),
+    "fctn_set_x": (ctypes.c_int, [_P, _P]),
+    "fctn_sweep": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(fctn_sweep_stats)]),
+    "fctn_sweep_many": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32]),
+    "fctn_complete": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
+                                     ctypes.POINTER(fctn_stats)]),
+    "fctn_get_history": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(fctn_sweep_stats)]),
+    "fctn_get_x": (ctypes.c_int, [_P, _P]),
+    "fctn_get_factor": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "fctn_step_gram_rhs": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "fctn_step_solve": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "fctn_step_reconstruct": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "fctn_step_x_update": (ctypes.c_int, [_P, _P, ctypes.POINTER(fctn_sweep_stats)]),
+    "fctn_mode_sizes": (ctypes.c_int, [_D, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64)]),
+    "fctn_destroy": (ctypes.c_int, [_P]),
+    "fctn_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+
+def lib():
+    """Load libfctn.so (built in-tree by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, where):
+    if status != OK:
+        raise FctnError(status, where)
+
+
+# --- thin wrappers with the C names --------------------------------------
+
+def fctn_status_str(status):
+    return lib().fctn_status_str(status).decode()
+
+
+def make_desc(dims, ranks, lam=1e-2, delta=0.5, rho=0.1, precision="f32", reuse=True,
+              order_policy=1):
+    d = fctn_desc()
+    N = len(dims)
+    d.order = N
+    for k, v in enumerate(dims):
+        d.dims[k] = int(v)
+    for b, r in enumerate(ranks):
+        d.ranks[b] = int(r)
+    lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), (N,))
+    delta = np.broadcast_to(np.asarray(delta, dtype=np.float64), (N,))
+    for k in range(N):
+        d.lambda_[k] = float(lam[k])
+        d.delta[k] = float(delta[k])
+    d.rho = float(rho)
+    d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    d.reuse = int(bool(reuse))
+    d.order_policy = int(order_policy)
+    return d
+
+
+def fctn_workspace_bytes(desc):
+    return lib().fctn_workspace_bytes(ctypes.byref(desc))
+
+
+def fctn_mode_sizes(desc, k):
+    s = ctypes.c_int64()
+    i = ctypes.c_int64()
+    _check(lib().fctn_mode_sizes(ctypes.byref(desc), k, ctypes.byref(s), ctypes.byref(i)),
+           "fctn_mode_sizes")
+    return s.value, i.value
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """One completion problem resident on the GPU (torch-owned workspace)."""
+
+    def __init__(self, dims, ranks, lam=1e-2, delta=0.5, rho=0.1, precision="f32", reuse=True,
+                 order_policy=1, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.dims = tuple(int(v) for v in dims)
+        self.ranks = tuple(int(r) for r in ranks)
+        self.precision = precision
+        self.desc = make_desc(dims, ranks, lam, delta, rho, precision, reuse, order_policy)
+        self.ws_bytes = fctn_workspace_bytes(self.desc)
+        if self.ws_bytes == 0:
+            raise FctnError(E_UNSUPPORTED if 2 <= len(dims) <= 8 else E_INVALID, "fctn_workspace_bytes")
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.elem = torch.float64 if precision == "f64" else torch.float32
+        h = ctypes.c_void_p()
+        _check(lib().fctn_plan(ctypes.byref(self.desc), _ptr(self.ws), self.ws_bytes,
+                               _stream_handle(self.stream), ctypes.byref(h)), "fctn_plan")
+        self.handle = h
+
+    # -- inputs -------------------------------------------------------------
+    def set_factors(self, factors):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in factors]
+        ptrs = (ctypes.POINTER(ctypes.c_double) * len(arrs))(
+            *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs])
+        _check(lib().fctn_set_factors(self.handle, ptrs), "fctn_set_factors")
+
+    def set_observed(self, Y, mask):
+        Y = self._dev(Y, self.elem)
+        mask = self._dev(mask, self.torch.uint8)
+        self._sync_inputs()
+        _check(lib().fctn_set_observed(self.handle, _ptr(Y), _ptr(mask)), "fctn_set_observed")
+
+    def set_x(self, X):
+        X = self._dev(X, self.elem)
+        self._sync_inputs()
+        _check(lib().fctn_set_x(self.handle, _ptr(X)), "fctn_set_x")
+        self._keep = X
+
+    # -- sweeps -------------------------------------------------------------
+    def sweep(self, n=1, stats=False):
+        st = fctn_sweep_stats() if stats else None
+        _check(lib().fctn_sweep(self.handle, int(n), ctypes.byref(st) if stats else None),
+               "fctn_sweep")
+        return st.as_dict() if stats else None
+
+    def complete(self, max_sweeps, tol=0.0, check_every=1, X_out=None):
+        st = fctn_stats()
+        _check(lib().fctn_complete(self.handle, int(max_sweeps), float(tol), int(check_every),
+                                   _ptr(X_out) if X_out is not None else None,
+                                   ctypes.byref(st)), "fctn_complete")
+        return {"sweeps_done": st.sweeps_done, "rel_change": st.rel_change,
+                "objective": st.objective}
+
+    def history(self, first, count):
+        arr = (fctn_sweep_stats * count)()
+        _check(lib().fctn_get_history(self.handle, int(first), int(count), arr),
+               "fctn_get_history")
+        return [a.as_dict() for a in arr]
+
+    # -- outputs ------------------------------------------------------------
+    def x(self):
+        out = self.torch.empty(self.dims, dtype=self.elem, device=self.device)
+        _check(lib().fctn_get_x(self.handle, _ptr(out)), "fctn_get_x")
+        self.stream.synchronize()
+        return out
+
+    def factor(self, k):
+        shape = factor_shape(self.dims, self.ranks, k)
+        out = self.torch.empty(shape, dtype=self.torch.float64, device=self.device)
+        _check(lib().fctn_get_factor(self.handle, int(k), _ptr(out)), "fctn_get_factor")
+        self.stream.synchronize()
+        return out
+
+    # -- single steps ---------------------------------------------------------
+    def mode_sizes(self, k):
+        return fctn_mode_sizes(self.desc, k)
+
+    def step_gram_rhs(self, k):
+        s, Ik = self.mode_sizes(k)
+        G = self.torch.empty((s, s), dtype=self.torch.float64, device=self.device)
+        B = self.torch.empty((Ik, s), dtype=self.torch.float64, device=self.device)
+        _check(lib().fctn_step_gram_rhs(self.handle, int(k), _ptr(G), _ptr(B)),
+               "fctn_step_gram_rhs")
+        self.stream.synchronize()
+        return G, B
+
+    def step_solve(self, k, G, B):
+        G = self._dev(G, self.torch.float64)
+        B = self._dev(B, self.torch.float64)
+        self._sync_inputs()
+        tr = ctypes.c_double()
+        _check(lib().fctn_step_solve(self.handle, int(k), _ptr(G), _ptr(B), ctypes.byref(tr)),
+               "fctn_step_solve")
+        return tr.value
+
+    def step_reconstruct(self, k):
+        Z = self.torch.empty(self.dims, dtype=self.elem, device=self.device)
+        _check(lib().fctn_step_reconstruct(self.handle, int(k), _ptr(Z)), "fctn_step_reconstruct")
+        self.stream.synchronize()
+        return Z
+
+    def step_x_update(self, Z):
+        Z = self._dev(Z, self.elem)
+        self._sync_inputs()
+        st = fctn_sweep_stats()
+        _check(lib().fctn_step_x_update(self.handle, _ptr(Z), ctypes.byref(st)),
+               "fctn_step_x_update")
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fctn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ----------------------------------------------------------------
+    def _dev(self, a, dtype):
+        torch = self.torch
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(np.ascontiguousarray(a))
+        return a.to(device=self.device, dtype=dtype).contiguous()
+
+    def _sync_inputs(self):
+        # inputs prepared on torch's current stream must be complete before the
+        # plan's stream reads them
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+
+def factor_shape(dims, ranks, k):
+    N = len(dims)
+    R = [[0] * N for _ in range(N)]
+    b = 0
+    for i in range(N):
+        for j in range(i + 1, N):
+            R[i][j] = R[j][i] = ranks[b]
+            b += 1
+    return tuple(dims[k] if j == k else R[k][j] for j in range(N))
+
+
+def sweep_many(plans, nsweeps):
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+    _check(lib().fctn_sweep_many(arr, len(plans), int(nsweeps)), "fctn_sweep_many")
