@@ -1,0 +1,189 @@
+"""Benchmark: PAM sweeps/s of trace-regularized FCTN completion on one MI355X.
+
+One step = one full PAM sweep (every factor update: sub-network generation,
+Gram + right-hand side, reduction, factor solve; then the reconstruction, the
+X/mask pass and the per-sweep scalars) over the whole synthetic tensor, with
+all inputs resident in HBM before the timed region.
+
+Default workload: the order-4 video-shaped tensor 144 x 176 x 3 x 50 with
+FCTN ranks R12 = R14 = R24 = 8, R13 = R23 = R34 = 3, sampling rate 0.05,
+float32 with float64 reductions and solves, reuse on (Algorithm 2 with the
+alternating factor order).
+
+Prints ONE JSON line.  `roofline` is for the kernel with the largest summed
+time (HIP events on the plan's stream over the timed region): algorithmic
+flops (or bytes) per launch / average launch time, against MI355X's
+published peak.  `cpu_baseline` is the float64 oracle on the host cores over
+a bounded number of sweeps of the same workload.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PAM sweeps/s + % MFMA peak; served completions/s with p50/p99 latency"
+PEAK = {  # MI355X published dense peaks
+    "f32": 157.3e12, "f64": 78.6e12, "bf16": 2.5e15, "bf16x3": 2.5e15, "hbm": 8.0e12,
+}
+WORKLOADS = {
+    "c3": ("c3", None, "video-shaped order-4 144x176x3x50, ranks (8,3,8,3,8,3), SR 0.05"),
+    "c2": ("c2", None, "color-image order-3 256x256x3, ranks (12,3,3), SR 0.1"),
+    "c4": ("c4", None, "multispectral order-3 512x512x31, ranks (16,8,8), SR 0.05"),
+    "c1": ("c1", None, "low-rank order-3 32x32x8, ranks (3,3,3), SR 0.3"),
+}
+DEFAULT_PREC = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f32"}
+MFMA_STAGES = ("gram_rhs", "reconstruct", "pair")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2510_22506_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision, stage):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if it is missing or was taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = t.get(f"{workload}/{precision}/{stage}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, sweeps):
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import pam
+    A0 = prob.A0
+    if prob.precision != "f64":
+        A0 = [a.astype(np.float32).astype(np.float64) for a in A0]
+    Y = prob.Y.astype(np.float64)
+    t0 = time.perf_counter()
+    pam.complete(Y, prob.mask != 0, prob.ranks, prob.lam, prob.delta, prob.rho, sweeps, A0,
+                 reuse=True, order_policy=1)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": sweeps / dt, "unit": "sweeps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{sweeps} sweeps of the same workload from the same initial factors "
+                      f"({dt:.1f} s, float64 NumPy, {os.cpu_count()} host CPUs visible)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--reuse", type=int, default=1)
+    ap.add_argument("--order-policy", type=int, default=1)
+    ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stages", action="store_true", help="add the per-stage breakdown")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU; multi-GPU sharding is design-only "
+              "(see the sharding section of the design notes). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2510_22506_amd import Plan
+    from workloads import make_problem
+
+    name, dims, desc = WORKLOADS[args.workload]
+    prec = args.precision or DEFAULT_PREC[name]
+    prob = make_problem(name, seed=0, precision=("f64" if prec == "f64" else "f32"))
+    plan = Plan(prob.dims, prob.ranks, prob.lam, prob.delta, prob.rho, precision=prec,
+                reuse=bool(args.reuse), order_policy=args.order_policy, device="cuda:0")
+    plan.set_factors(prob.A0)
+    plan.set_observed(torch.from_numpy(prob.Y), torch.from_numpy(prob.mask))
+    torch.cuda.synchronize()
+
+    plan.sweep(args.warmup)
+    torch.cuda.synchronize()
+    plan.profile_enable(True)
+    plan.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.sweep(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile_read(reset=True)
+    dt = t1 - t0
+    value = args.steps / dt
+
+    total_flops = sum(v["flops"] for k, v in prof.items() if k in MFMA_STAGES)
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    avg_s = d["ms"] / 1e3 / max(d["launches"], 1)
+    if dom in MFMA_STAGES:
+        achieved = d["flops"] / max(d["launches"], 1) / avg_s
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK[prec]}
+    else:
+        achieved = d["bytes"] / max(d["launches"], 1) / avg_s
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": achieved / PEAK["hbm"]}
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["launches"] = d["launches"]
+    roof["traffic"] = measured_traffic(name, prec, dom)
+
+    xp = prof["x_update"]
+    x_avg = xp["ms"] / 1e3 / max(xp["launches"], 1)
+    x_bw = xp["bytes"] / max(xp["launches"], 1) / x_avg if x_avg > 0 else 0.0
+    roof_x = {"bound": "hbm", "kernel": "x_update", "achieved": x_bw / 1e9,
+              "peak": PEAK["hbm"] / 1e9, "unit": "GB/s", "frac": x_bw / PEAK["hbm"],
+              "avg_launch_us": x_avg * 1e6,
+              "traffic": measured_traffic(name, prec, "x_update")}
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": f"{name}: {desc}", "dims": list(prob.dims),
+                   "ranks": list(prob.ranks), "precision": prec, "reuse": bool(args.reuse),
+                   "order_policy": args.order_policy, "lambda": prob.lam, "rho": prob.rho,
+                   "delta": prob.delta},
+        "tflops_contractions": total_flops / dt / 1e12,
+        "roofline": roof,
+        "roofline_xpass": roof_x,
+    }
+    if args.stages:
+        line["stages"] = {k: {"launches": v["launches"], "ms_total": v["ms"],
+                              "us_per_launch": v["ms"] * 1e3 / max(v["launches"], 1),
+                              "gflop": v["flops"] / 1e9}
+                          for k, v in prof.items() if v["launches"]}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_sweeps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

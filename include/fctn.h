@@ -187,6 +187,38 @@ fctn_status fctn_step_x_update(fctn_plan_t plan, const void* Z_dev,
 fctn_status fctn_mode_sizes(const fctn_desc* desc, int32_t k, int64_t* s_k,
                             int64_t* I_k);
 
+/* ---- per-kernel timing ---------------------------------------------------
+ * Stages, one per kernel of a sweep: */
+enum {
+  FCTN_STAGE_PAIR = 0,        /* pair tensor of the reuse mechanism (N = 4)  */
+  FCTN_STAGE_GRAM_RHS = 1,    /* fused M_k generation + Gram + RHS (eq. 5)   */
+  FCTN_STAGE_REDUCE = 2,      /* float64 split-K reduction (+ rho A_k)        */
+  FCTN_STAGE_SOLVE = 3,       /* per-class Cholesky solves (eq. 5-8)          */
+  FCTN_STAGE_BACKTRANSFORM = 4, /* A = Q A~, fold (eq. 9), casts             */
+  FCTN_STAGE_RECONSTRUCT = 5, /* Z = A_last M'_last (Algorithm 2, X step)    */
+  FCTN_STAGE_XUPDATE = 6,     /* eq. 10 select + norm partials               */
+  FCTN_STAGE_STATS = 7,       /* per-sweep scalars                           */
+  FCTN_NSTAGES = 8
+};
+
+typedef struct {
+  int64_t launches[FCTN_NSTAGES];
+  double ms[FCTN_NSTAGES];      /* summed kernel time from HIP events         */
+  double flops[FCTN_NSTAGES];   /* summed algorithmic flops of those launches */
+  double bytes[FCTN_NSTAGES];   /* summed algorithmic HBM bytes               */
+} fctn_profile;
+
+/* Enable (1) or disable (0) per-launch HIP event pairs on the plan's stream.
+ * Algorithmic flops count 2 per multiply-add of the paper's dense products
+ * (sub-network generation, the full s_k x s_k Gram, the RHS, the
+ * reconstruction, the pair tensors); algorithmic bytes count each tensor
+ * read or written once. */
+fctn_status fctn_profile_enable(fctn_plan_t plan, int32_t enable);
+
+/* Accumulate every recorded launch into *out (synchronizes); reset != 0
+ * clears the recorded launches afterwards. */
+fctn_status fctn_profile_read(fctn_plan_t plan, fctn_profile* out, int32_t reset);
+
 /* Release the plan's host state (the workspace stays the caller's). */
 fctn_status fctn_destroy(fctn_plan_t plan);
 

@@ -3,6 +3,7 @@
 // pair-tensor cache of the reuse mechanism and the alternating factor order)
 // and the C ABI declared in fctn.h.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -46,7 +47,19 @@ struct ModeInfo {
   MGen mg;          // strides/sizes; U/V pointers resolved at launch
   XView xv;
   GramGeom geom;
+  RecGeom rg;
   int ncls;
+};
+
+struct ProfRec {
+  int stage;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
+struct ProfState {
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
 };
 
 }  // namespace
@@ -74,6 +87,7 @@ struct fctn_plan_s {
   void* part;
   double *G, *B, *At;
   double* Q[4];
+  double* Qt[4];
   double* lamcol[4];
   double* trace_part;
   int max_cls;
@@ -89,6 +103,8 @@ struct fctn_plan_s {
   bool pvalid[2];
   fctn_status sticky;
   bool debug;
+  bool prof_on;
+  ProfState* prof;
 };
 
 namespace {
@@ -207,6 +223,77 @@ void setup_modes(fctn_plan_s* P) {
   }
 }
 
+inline int ld_mod(int x, int r) { return x + ((r - x % 64) % 64 + 64) % 64; }
+
+// Operand slabs: [kap][p] (p contiguous; ld = 16 mod 64) unless kap is the
+// contiguous index in HBM, then [p][kap] (ld = 4 mod 64).  Both orders give
+// bank-conflict-free MFMA operand reads.
+void fill_tile(const MGen& mg, int TCu, int TCv, TileGeom* tg) {
+  tg->TCu = TCu;
+  tg->TCv = TCv;
+  tg->tcol = TCu * TCv;
+  tg->tcolp = (tg->tcol + 3) / 4 * 4;
+  tg->Pu = mg.Ru * TCu;
+  tg->Qv = mg.Rv * TCv;
+  tg->Pp = pad16(tg->Pu);
+  tg->Qp = pad16(tg->Qv);
+  tg->Kp = (mg.K + 3) / 4 * 4;
+  if (mg.u_k == 1 && mg.K > 1) {
+    tg->us_k = 1; tg->us_p = ld_mod(tg->Kp, 4); tg->u_len = tg->Pp * tg->us_p;
+  } else {
+    tg->us_p = 1; tg->us_k = ld_mod(tg->Pp, 16); tg->u_len = tg->Kp * tg->us_k;
+  }
+  if (mg.v_k == 1 && mg.K > 1) {
+    tg->vs_k = 1; tg->vs_q = ld_mod(tg->Kp, 4); tg->v_len = tg->Qp * tg->vs_q;
+  } else {
+    tg->vs_q = 1; tg->vs_k = ld_mod(tg->Qp, 16); tg->v_len = tg->Kp * tg->vs_k;
+  }
+  tg->nTileU = (mg.Cu + TCu - 1) / TCu;
+  tg->nTileV = (mg.Cv + TCv - 1) / TCv;
+  tg->nColTiles = tg->nTileU * tg->nTileV;
+}
+
+// Pick the column tile minimizing MFMA instructions (padding included) per
+// real column, plus a fixed per-tile overhead, within the LDS budget.
+// extra_mfma(tg) is the consumer's work per tile; lds(tg) its LDS bytes.
+template <class Extra, class Lds>
+bool choose_tile(const MGen& mg, int mg_repeat, Extra extra_mfma, Lds lds, TileGeom* best) {
+  static const int cv_c[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20, 24, 25, 30, 32, 40, 48, 50, 64};
+  static const int cu_c[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  double best_cost = 1e300;
+  bool found = false;
+  std::vector<int> cvs;
+  for (int v : cv_c)
+    if (v <= mg.Cv) cvs.push_back(v);
+  if (mg.Cv <= 64) cvs.push_back((int)mg.Cv);
+  std::vector<int> cus;
+  for (int u : cu_c)
+    if (u <= mg.Cu) cus.push_back(u);
+  if (mg.Cu <= 64) cus.push_back((int)mg.Cu);
+  for (int TCv : cvs) {
+    for (int TCu : cus) {
+      const int tcol = TCu * TCv;
+      if (tcol > 256) continue;
+      TileGeom tg;
+      fill_tile(mg, TCu, TCv, &tg);
+      const size_t bytes = lds(tg);
+      if (bytes > (size_t)gram_max_lds_bytes()) continue;
+      const double mgen = (double)(tg.Pp / 16) * (tg.Qp / 16) * (tg.Kp / 4) * mg_repeat;
+      const double real = ((double)mg.Cu / tg.nTileU) * ((double)mg.Cv / tg.nTileV);
+      double cost = (mgen + extra_mfma(tg) + 24.0) / real;
+      if (bytes > 80 * 1024) cost *= 1.15;   // one workgroup per CU
+      const double par = (double)tg.nColTiles * mg_repeat;
+      if (par < 512.0) cost *= 512.0 / std::max(par, 1.0);   // too few tiles to fill 256 CUs
+      if (cost < best_cost * 0.999) {
+        best_cost = cost;
+        *best = tg;
+        found = true;
+      }
+    }
+  }
+  return found;
+}
+
 bool setup_geom(ModeInfo& m, size_t es) {
   GramGeom& g = m.geom;
   g.s = (int)m.s;
@@ -230,22 +317,38 @@ bool setup_geom(ModeInfo& m, size_t es) {
   g.xrows = xmax;
   g.ldm = ld_pad(g.sp);
   g.ldx = ld_pad(std::max(xmax, 16));
-  g.tc = 0;
-  for (int tc : {32, 16}) {
-    const size_t lds = (size_t)tc * (g.ldm + g.ldx) * es;
-    if (lds <= (size_t)gram_max_lds_bytes()) {
-      g.tc = tc;
-      g.lds_bytes = lds;
-      break;
-    }
-  }
-  if (g.tc == 0) return false;
-  g.nColTiles = (m.C + g.tc - 1) / g.tc;
+  auto gram_lds = [&](const TileGeom& tg) {
+    return (size_t)(tg.u_len + tg.v_len + (size_t)tg.tcolp * (g.ldm + g.ldx)) * es;
+  };
+  auto gram_work = [&](const TileGeom& tg) { return (double)g.nTiles * (tg.tcolp / 4); };
+  if (!choose_tile(m.mg, g.nGroups, gram_work, gram_lds, &g.tg)) return false;
+  g.lds_bytes = gram_lds(g.tg);
   int64_t ns = std::max<int64_t>(1, kTargetGramWGs / g.nGroups);
-  ns = std::min<int64_t>(ns, g.nColTiles);
-  g.colTilesPerSplit = (g.nColTiles + ns - 1) / ns;
-  g.nSplit = (int32_t)((g.nColTiles + g.colTilesPerSplit - 1) / g.colTilesPerSplit);
-  return true;
+  ns = std::min<int64_t>(ns, g.tg.nColTiles);
+  g.colTilesPerSplit = (g.tg.nColTiles + ns - 1) / ns;
+  g.nSplit = (int32_t)((g.tg.nColTiles + g.colTilesPerSplit - 1) / g.colTilesPerSplit);
+
+  RecGeom& r = m.rg;
+  r.s = g.s;
+  r.sp = g.sp;
+  r.Ik = g.Ik;
+  r.ip = g.ip;
+  const int lda = ld_mod(r.sp, 16);
+  const bool stage_a = (size_t)r.ip * lda * es <= 64 * 1024;
+  r.lda = stage_a ? lda : 0;
+  auto rec_lds = [&](const TileGeom& tg) {
+    const int ldm = ld_mod(std::max(r.sp, 4), 4);
+    return (size_t)(tg.u_len + tg.v_len + (size_t)tg.tcolp * ldm + (size_t)r.ip * r.lda) * es;
+  };
+  auto rec_work = [&](const TileGeom& tg) {
+    return (double)(r.ip / 16) * (pad16(tg.tcolp) / 16) * (r.sp / 4);
+  };
+  if (!choose_tile(m.mg, 1, rec_work, rec_lds, &r.tg)) return false;
+  r.tg.tcolp = pad16(r.tg.tcol);
+  r.ldm = ld_mod(std::max(r.sp, 4), 4);
+  r.lds_bytes = rec_lds(r.tg);
+  r.nblk = (int32_t)std::min<int64_t>(r.tg.nColTiles, 2048);
+  return r.lds_bytes <= (size_t)gram_max_lds_bytes();
 }
 
 // carve (or measure, base == nullptr) the workspace; returns bytes
@@ -268,6 +371,7 @@ size_t carve(fctn_plan_s* P, char* base) {
     P->Aw[k] = c.take(P->fnum[k] * es);
     P->Au[k] = c.take(P->fnum[k] * es);
     P->Q[k] = (double*)c.take(m.Ik * m.Ik * sizeof(double));
+    P->Qt[k] = (double*)c.take(m.Ik * m.Ik * sizeof(double));
     P->lamcol[k] = (double*)c.take(m.Ik * sizeof(double));
     smax = std::max(smax, m.s);
     imax = std::max(imax, m.Ik);
@@ -310,6 +414,19 @@ bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
     if (!solve_supported((int32_t)P->mode[k].s)) return false;
     if (!setup_geom(P->mode[k], P->es)) return false;
   }
+  const char* gp = getenv("FCTN_GEOM");
+  if (gp && gp[0] == '1') {
+    for (int k = 0; k < P->N; ++k) {
+      const GramGeom& g = P->mode[k].geom;
+      const RecGeom& r = P->mode[k].rg;
+      fprintf(stderr,
+              "mode %d: s %d Ik %d | gram tile %dx%d (P %d/%d Q %d/%d K %d) cols %lld "
+              "groups %d splits %d lds %zu | rec tile %dx%d lds %zu stageA %d blocks %d\n",
+              k, g.s, g.Ik, g.tg.TCu, g.tg.TCv, g.tg.Pu, g.tg.Pp, g.tg.Qv, g.tg.Qp, g.tg.Kp,
+              (long long)g.tg.nColTiles, g.nGroups, g.nSplit, g.lds_bytes, r.tg.TCu, r.tg.TCv,
+              r.lds_bytes, r.lda > 0, r.nblk);
+    }
+  }
   return true;
 }
 
@@ -329,6 +446,33 @@ const void* src_ptr(fctn_plan_s* P, int src) {
     }                                                         \
   } while (0)
 
+hipEvent_t prof_event(fctn_plan_s* P) {
+  hipEvent_t e = nullptr;
+  if (!P->prof->pool.empty()) {
+    e = P->prof->pool.back();
+    P->prof->pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+// event pair around one launch when profiling is on
+#define FCTN_TIMED(P, stage, flops, bytes, expr)                         \
+  do {                                                                   \
+    hipEvent_t a_ = nullptr, b_ = nullptr;                               \
+    if ((P)->prof_on) {                                                  \
+      a_ = prof_event(P);                                                \
+      b_ = prof_event(P);                                                \
+      if (a_) hipEventRecord(a_, (P)->st);                               \
+    }                                                                    \
+    FCTN_LAUNCH(P, expr);                                                \
+    if (a_ && b_) {                                                      \
+      hipEventRecord(b_, (P)->st);                                       \
+      (P)->prof->recs.push_back(ProfRec{(stage), a_, b_, (double)(flops), (double)(bytes)}); \
+    }                                                                    \
+  } while (0)
+
 // pair p is built from factors (0,1) for p = 0 and (2,3) for p = 1
 fctn_status ensure_pair(fctn_plan_s* P, int p, bool force) {
   const int fa = p == 0 ? 0 : 2, fb = fa + 1;
@@ -337,7 +481,9 @@ fctn_status ensure_pair(fctn_plan_s* P, int p, bool force) {
   PairDesc pd = P->pd[p];
   pd.Fa = P->Aw[fa];
   pd.Fb = P->Aw[fb];
-  FCTN_LAUNCH(P, launch_pair(P->prec, pd, P->P[p], P->st));
+  FCTN_TIMED(P, FCTN_STAGE_PAIR, 2.0 * P->pnum[p] * pd.K,
+             (double)(P->fnum[fa] + P->fnum[fb] + P->pnum[p]) * P->es,
+             launch_pair(P->prec, pd, P->P[p], P->st));
   P->pvalid[p] = true;
   P->pver[p][0] = P->fver[fa];
   P->pver[p][1] = P->fver[fb];
@@ -367,19 +513,32 @@ fctn_status gram_rhs(fctn_plan_s* P, int k, double* G, double* B) {
   if (s != FCTN_OK) return s;
   const ModeInfo& m = P->mode[k];
   const MGen g = resolved_mgen(P, k);
-  FCTN_LAUNCH(P, launch_gram_rhs(P->prec, g, P->X, m.xv, m.geom, P->part, P->st));
-  FCTN_LAUNCH(P, launch_reduce_gb(P->prec, m.geom, P->part, P->A64[k], m.spost, P->d.rho, G, B,
-                                  P->st));
+  const double sC = (double)m.s * m.C;
+  const double acc_es = P->prec == FCTN_F64 ? 8.0 : 4.0;
+  const double part_bytes = (double)m.geom.nSplit * m.geom.nTiles * 256 * acc_es;
+  FCTN_TIMED(P, FCTN_STAGE_GRAM_RHS, 2.0 * sC * (m.mg.K + m.s + m.Ik),
+             (double)P->numel * P->es + part_bytes,
+             launch_gram_rhs(P->prec, g, P->X, m.xv, m.geom, P->part, P->st));
+  FCTN_TIMED(P, FCTN_STAGE_REDUCE, (double)m.geom.nSplit * (m.s * m.s + m.Ik * m.s),
+             part_bytes + 8.0 * (m.s * m.s + 2 * m.Ik * m.s),
+             launch_reduce_gb(P->prec, m.geom, P->part, P->A64[k], m.spost, P->d.rho, G, B,
+                              P->st));
   return FCTN_OK;
 }
 
 fctn_status solve(fctn_plan_s* P, int k, const double* G, const double* B) {
   const ModeInfo& m = P->mode[k];
-  FCTN_LAUNCH(P, launch_solve_classes(G, B, P->Q[k], (int32_t)m.Ik, (int32_t)m.s,
-                                      P->d.lambda[k], P->d.delta[k], P->d.rho, P->At,
-                                      P->trace_part + (size_t)k * P->max_cls, P->st));
-  FCTN_LAUNCH(P, launch_backtransform(P->prec, P->Q[k], P->At, (int32_t)m.Ik, (int32_t)m.s,
-                                      m.spost, P->A64[k], P->Aw[k], P->Au[k], P->st));
+  const double s3 = (double)m.s * m.s * m.s;
+  FCTN_TIMED(P, FCTN_STAGE_SOLVE,
+             m.ncls * (s3 / 3.0 + 4.0 * m.s * m.s) + 4.0 * m.Ik * m.Ik * m.s,
+             8.0 * (m.s * m.s + 2.0 * m.Ik * m.s + m.Ik * m.Ik),
+             launch_solve_classes(G, B, P->Qt[k], (int32_t)m.Ik, (int32_t)m.s, P->d.lambda[k],
+                                  P->d.delta[k], P->d.rho, P->At,
+                                  P->trace_part + (size_t)k * P->max_cls, P->st));
+  FCTN_TIMED(P, FCTN_STAGE_BACKTRANSFORM, 2.0 * m.Ik * m.Ik * m.s,
+             8.0 * (m.Ik * m.Ik + 2.0 * m.Ik * m.s) + 2.0 * m.Ik * m.s * P->es,
+             launch_backtransform(P->prec, P->Q[k], P->At, (int32_t)m.Ik, (int32_t)m.s,
+                                  m.spost, P->A64[k], P->Aw[k], P->Au[k], P->st));
   P->fver[k]++;
   return FCTN_OK;
 }
@@ -392,15 +551,20 @@ fctn_status reconstruct(fctn_plan_s* P, int k, void* Z) {
   }
   const ModeInfo& m = P->mode[k];
   const MGen g = resolved_mgen(P, k);
-  FCTN_LAUNCH(P, launch_reconstruct(P->prec, g, P->Au[k], Z, m.xv, (int32_t)m.s, m.C, P->st));
+  FCTN_TIMED(P, FCTN_STAGE_RECONSTRUCT, 2.0 * (double)m.s * m.C * (m.mg.K + m.Ik),
+             (double)P->numel * P->es,
+             launch_reconstruct(P->prec, g, P->Au[k], Z, m.xv, m.rg, P->st));
   return FCTN_OK;
 }
 
 fctn_status x_update(fctn_plan_s* P, const void* Z, double* slot, bool with_trace) {
-  FCTN_LAUNCH(P, launch_x_update(P->prec, P->X, Z, P->bits, P->d.rho, P->numel, kXBlocks,
-                                 P->xpart, P->st));
-  FCTN_LAUNCH(P, launch_stats(P->xpart, kXBlocks, P->trace_part, P->lam_half, P->ncls_dev,
-                              with_trace ? P->N : 0, P->max_cls, slot, P->st));
+  FCTN_TIMED(P, FCTN_STAGE_XUPDATE, 5.0 * P->numel,
+             3.0 * P->numel * P->es + P->numel / 8.0,
+             launch_x_update(P->prec, P->X, Z, P->bits, P->d.rho, P->numel, kXBlocks, P->xpart,
+                             P->st));
+  FCTN_TIMED(P, FCTN_STAGE_STATS, 3.0 * kXBlocks, 24.0 * kXBlocks,
+             launch_stats(P->xpart, kXBlocks, P->trace_part, P->lam_half, P->ncls_dev,
+                          with_trace ? P->N : 0, P->max_cls, slot, P->st));
   return FCTN_OK;
 }
 
@@ -496,8 +660,8 @@ fctn_status fctn_plan(const fctn_desc* desc, void* ws_dev, size_t ws_bytes, void
   std::vector<double> lh(P->N);
   std::vector<int32_t> nc(P->N);
   for (int k = 0; k < P->N && ok; ++k) {
-    ok = launch_build_basis(P->Q[k], P->lamcol[k], (int32_t)P->mode[k].Ik, desc->delta[k],
-                            P->st) == hipSuccess;
+    ok = launch_build_basis(P->Q[k], P->Qt[k], P->lamcol[k], (int32_t)P->mode[k].Ik,
+                            desc->delta[k], P->st) == hipSuccess;
     lh[k] = 0.5 * desc->lambda[k];
     nc[k] = P->mode[k].ncls;
   }
@@ -727,9 +891,53 @@ fctn_status fctn_step_x_update(fctn_plan_t P, const void* Z_dev, fctn_sweep_stat
   return FCTN_OK;
 }
 
+fctn_status fctn_profile_enable(fctn_plan_t P, int32_t enable) {
+  if (!P) return FCTN_E_INVALID;
+  if (enable && !P->prof) {
+    P->prof = new (std::nothrow) ProfState;
+    if (!P->prof) return FCTN_E_NOMEM;
+  }
+  P->prof_on = enable != 0;
+  return FCTN_OK;
+}
+
+fctn_status fctn_profile_read(fctn_plan_t P, fctn_profile* out, int32_t reset) {
+  if (!P || !out) return FCTN_E_INVALID;
+  memset(out, 0, sizeof(*out));
+  if (!P->prof) return FCTN_OK;
+  if (hipStreamSynchronize(P->st) != hipSuccess) {
+    P->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  for (const ProfRec& r : P->prof->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return FCTN_E_DEVICE;
+    out->launches[r.stage] += 1;
+    out->ms[r.stage] += ms;
+    out->flops[r.stage] += r.flops;
+    out->bytes[r.stage] += r.bytes;
+  }
+  if (reset) {
+    for (const ProfRec& r : P->prof->recs) {
+      P->prof->pool.push_back(r.a);
+      P->prof->pool.push_back(r.b);
+    }
+    P->prof->recs.clear();
+  }
+  return FCTN_OK;
+}
+
 fctn_status fctn_destroy(fctn_plan_t P) {
   if (!P) return FCTN_E_INVALID;
   hipStreamSynchronize(P->st);
+  if (P->prof) {
+    for (const ProfRec& r : P->prof->recs) {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : P->prof->pool) hipEventDestroy(e);
+    delete P->prof;
+  }
   delete P;
   return FCTN_OK;
 }

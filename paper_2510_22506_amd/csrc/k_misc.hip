@@ -87,8 +87,8 @@ hipError_t launch_cast_factor(int prec, const double* A64, void* Aw, void* Au, i
 // c (1 <= c < n/2); for even n the last column alternates in sign.  Column
 // eigenvalue: delta + 4 sin^2(pi c / n).  Q is n x n row-major (Q[i][col]).
 // ---------------------------------------------------------------------------
-__global__ void basis_k(double* __restrict__ Q, double* __restrict__ lam_col, int32_t n,
-                        double delta) {
+__global__ void basis_k(double* __restrict__ Q, double* __restrict__ Qt,
+                        double* __restrict__ lam_col, int32_t n, double delta) {
   const int64_t nn = (int64_t)n * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -108,6 +108,7 @@ __global__ void basis_k(double* __restrict__ Q, double* __restrict__ lam_col, in
       v = sqrt(2.0 / n) * ((col & 1) ? cospi(ang) : sinpi(ang));
     }
     Q[e] = v;
+    Qt[(int64_t)col * n + i] = v;
     if (i == 0) {
       const double sn = sinpi((double)c / (double)n);
       lam_col[col] = delta + 4.0 * sn * sn;
@@ -115,11 +116,11 @@ __global__ void basis_k(double* __restrict__ Q, double* __restrict__ lam_col, in
   }
 }
 
-hipError_t launch_build_basis(double* Q, double* lam_col, int32_t n, double delta,
+hipError_t launch_build_basis(double* Q, double* Qt, double* lam_col, int32_t n, double delta,
                               hipStream_t st) {
   const int64_t nn = (int64_t)n * n;
   const int nb = (int)(cdiv(nn, 256) < 1024 ? cdiv(nn, 256) : 1024);
-  basis_k<<<nb, 256, 0, st>>>(Q, lam_col, n, delta);
+  basis_k<<<nb, 256, 0, st>>>(Q, Qt, lam_col, n, delta);
   return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@
 // solution as eq. 8 (the shifted matrix is positive definite), reached
 // without an eigendecomposition of G.  backtransform_k forms A = Q A~ and
 // stores it folded (eq. 9) in float64 and in the working precision.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -23,14 +25,16 @@ int solve_supported(int32_t s) { return s >= 1 && s <= 192; }
 template <int SB>
 __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict__ G,
                                                         const double* __restrict__ B,
-                                                        const double* __restrict__ Q, int Ik,
+                                                        const double* __restrict__ Qt, int Ik,
                                                         int s, double lam, double delta,
                                                         double rho, double* __restrict__ At,
                                                         double* __restrict__ trace_part) {
-  constexpr int RA = SB + 1;
-  __shared__ double colbuf[2][32 * RA];
+  __shared__ double colbuf[2][32 * SB];
   __shared__ double rhs[2][32 * SB];
   __shared__ double diag[32 * SB];
+  __shared__ double rdiag[32 * SB];
+  __shared__ double red[16];
+  extern __shared__ double Lp[];   // s (s + 1) / 2 packed lower factor
   const int c = blockIdx.x;
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5, lane = tid & 63, wave = tid >> 6;
 
@@ -44,140 +48,192 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
   const double Lam = delta + 4.0 * sn * sn;
   const double sigma = lam * Lam + rho;
 
-  // b~_v[m] = sum_i Q[i][v] B[i][m]
-  for (int m = wave; m < s; m += 16) {
-    double p0 = 0.0, p1 = 0.0;
-    for (int i = lane; i < Ik; i += 64) {
-      const double b = B[(int64_t)i * s + m];
-      p0 += Q[(int64_t)i * Ik + v0] * b;
-      p1 += Q[(int64_t)i * Ik + v1] * b;
+  // b~_v[m] = sum_i Q[i][v] B[i][m]: output o = (v, m) gets nsub threads that
+  // each sum an interleaved slice of i (reads coalesced over m); the slices
+  // are combined in a fixed order through LDS (the L buffer, unused yet)
+  {
+    const int nout = 2 * s;
+    const int nsub = 1024 / nout;
+    const int o = tid % nout, sub = tid / nout;
+    if (sub < nsub) {
+      const int v = o >= s ? 1 : 0, m = o - v * s;
+      const double* q = Qt + (int64_t)(v ? v1 : v0) * Ik;
+      double p = 0.0;
+      for (int i = sub; i < Ik; i += nsub) p += q[i] * B[(int64_t)i * s + m];
+      Lp[sub * nout + o] = p;
     }
-    p0 = wave_sum(p0);
-    p1 = wave_sum(p1);
-    if (lane == 0) {
-      rhs[0][m] = p0;
-      rhs[1][m] = p1;
+    __syncthreads();
+    if (tid < nout) {
+      double p = 0.0;
+      for (int k = 0; k < nsub; ++k) p += Lp[k * nout + tid];
+      rhs[tid >= s ? 1 : 0][tid >= s ? tid - s : tid] = p;
     }
   }
-  __syncthreads();
 
-  double H[RA][SB];
+  // H = G + sigma I (lower part), 32x32 cyclic: thread (ty, tx) holds rows
+  // ty + 32a and columns tx + 32b
+  double H[SB][SB];
 #pragma unroll
-  for (int a = 0; a < RA; ++a) {
+  for (int a = 0; a < SB; ++a) {
     const int i = ty + 32 * a;
 #pragma unroll
     for (int b = 0; b < SB; ++b) {
       const int m = tx + 32 * b;
-      double v = 0.0;
-      if (i < s && m <= i) v = G[(int64_t)i * s + m] + (i == m ? sigma : 0.0);
-      else if (i >= s && i < s + nv && m < s) v = rhs[i - s][m];
-      H[a][b] = v;
+      H[a][b] = (i < s && m <= i) ? G[(int64_t)i * s + m] + (i == m ? sigma : 0.0) : 0.0;
     }
   }
+  __syncthreads();
 
+  // right-looking Cholesky; the class right-hand sides ride along as extra
+  // rows kept in rhs[] (forward substitution): after column j their entries
+  // beyond j are updated with l_{rhs,j} l_{m,j}, l_{rhs,j} = rhs[v][j] / sqrt(d_j).
+  // Register blocks that are finished (all rows or columns <= j) or above
+  // the diagonal are skipped; both tests are uniform across a wave.
   for (int j = 0; j < s; ++j) {
     const int jb = j >> 5, jt = j & 31;
     double* cb = colbuf[j & 1];
     if (tx == jt) {
 #pragma unroll
-      for (int a = 0; a < RA; ++a) {
+      for (int a = 0; a < SB; ++a) {
         const int i = ty + 32 * a;
-        if (i >= j && i < s + nv) {
+        if (a >= jb && i >= j && i < s) {
 #pragma unroll
-          for (int b = 0; b < SB; ++b)
-            if (b == jb) cb[i] = H[a][b];
+          for (int b = 0; b <= a; ++b)
+            if (b == jb) {
+              cb[i] = H[a][b];
+              if (i == j) {   // the one thread holding the pivot
+                const double sq = sqrt(H[a][b]);
+                diag[j] = sq;
+                rdiag[j] = 1.0 / sq;
+              }
+            }
         }
       }
     }
     __syncthreads();
-    const double d = cb[j];
-    const double sd = sqrt(d);
-    const double rs = 1.0 / sd;
+    const double sd = diag[j];
+    const double rs = rdiag[j];
     double lm[SB];
 #pragma unroll
     for (int b = 0; b < SB; ++b) {
       const int m = tx + 32 * b;
-      lm[b] = (m > j && m < s) ? cb[m] * rs : 0.0;
+      lm[b] = (32 * b + 31 > j && m > j && m < s) ? cb[m] * rs : 0.0;
     }
 #pragma unroll
-    for (int a = 0; a < RA; ++a) {
+    for (int a = 0; a < SB; ++a) {
+      if (32 * a + 31 <= j) continue;
       const int i = ty + 32 * a;
-      if (i > j && i < s + nv) {
+      if (i > j && i < s) {
         const double li = cb[i] * rs;
 #pragma unroll
-        for (int b = 0; b < SB; ++b) {
+        for (int b = 0; b <= a; ++b) {
+          if (32 * b + 31 <= j) continue;
           const int m = tx + 32 * b;
-          if (m > j && m <= i && m < s) H[a][b] -= li * lm[b];
+          if (m > j && m <= i) H[a][b] -= li * lm[b];
         }
+      }
+    }
+    if (ty < nv) {
+      const double yj = rhs[ty][j] * rs;
+#pragma unroll
+      for (int b = 0; b < SB; ++b) {
+        if (32 * b + 31 <= j) continue;
+        const int m = tx + 32 * b;
+        if (m > j && m < s) rhs[ty][m] -= yj * lm[b];
       }
     }
     if (tx == jt) {
 #pragma unroll
-      for (int a = 0; a < RA; ++a) {
+      for (int a = 0; a < SB; ++a) {
         const int i = ty + 32 * a;
 #pragma unroll
-        for (int b = 0; b < SB; ++b) {
+        for (int b = 0; b <= a; ++b) {
           if (b == jb) {
             if (i == j) H[a][b] = sd;
-            else if (i > j && i < s + nv) H[a][b] = cb[i] * rs;
+            else if (i > j && i < s) H[a][b] = cb[i] * rs;
           }
         }
       }
     }
-    if (tid == 0) diag[j] = sd;
   }
-  __syncthreads();
-
-  // forward-substitution results live in the appended rows: move them to rhs[]
+  // L to LDS (packed lower: row i starts at i (i + 1) / 2)
 #pragma unroll
-  for (int a = 0; a < RA; ++a) {
+  for (int a = 0; a < SB; ++a) {
     const int i = ty + 32 * a;
-    if (i >= s && i < s + nv) {
 #pragma unroll
-      for (int b = 0; b < SB; ++b) {
-        const int m = tx + 32 * b;
-        if (m < s) rhs[i - s][m] = H[a][b];
+    for (int b = 0; b <= a; ++b) {
+      const int m = tx + 32 * b;
+      if (i < s && m <= i) Lp[i * (i + 1) / 2 + m] = H[a][b];
+    }
+  }
+  __syncthreads();
+  // y = forward-substitution result
+  for (int m = tid; m < s; m += 1024) {
+    rhs[0][m] *= rdiag[m];
+    rhs[1][m] *= rdiag[m];
+  }
+  __syncthreads();
+
+  // back substitution L^T x = y in one wave, column-oriented: lane l keeps
+  // y_i for i = l + 64 q in registers; x_m is broadcast from its owner lane
+  // with readlane, then every lane removes L[m][i] x_m from its y_i (i < m)
+  if (wave == 0) {
+    constexpr int NQ = (32 * SB + 63) / 64;
+    double y0[NQ], y1[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + 64 * q;
+      y0[q] = i < s ? rhs[0][i] : 0.0;
+      y1[q] = i < s ? rhs[1][i] : 0.0;
+    }
+    for (int m = s - 1; m >= 0; --m) {
+      const int owner = m & 63, qm = m >> 6;
+      double ym0 = 0.0, ym1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q == qm) {
+          ym0 = y0[q];
+          ym1 = y1[q];
+        }
+      const double rd = rdiag[m];
+      const double x0 = bcast_lane(ym0, owner) * rd;
+      const double x1 = bcast_lane(ym1, owner) * rd;
+      const double* Lrow = Lp + m * (m + 1) / 2;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int i = lane + 64 * q;
+        if (i < m) {
+          const double l = Lrow[i];
+          y0[q] -= l * x0;
+          y1[q] -= l * x1;
+        } else if (i == m) {
+          y0[q] = x0;
+          y1[q] = x1;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + 64 * q;
+      if (i < s) {
+        rhs[0][i] = y0[q];
+        rhs[1][i] = y1[q];
       }
     }
   }
   __syncthreads();
-
-  // back substitution L^T x = y: rhs[v][i] -= L[m][i] x_m for i < m
-  for (int m = s - 1; m >= 0; --m) {
-    if (ty == (m & 31)) {
-      const int am = m >> 5;
-      const double x0 = rhs[0][m] / diag[m];
-      const double x1 = rhs[1][m] / diag[m];
-#pragma unroll
-      for (int a = 0; a < RA; ++a) {
-        if (a == am) {
-#pragma unroll
-          for (int b = 0; b < SB; ++b) {
-            const int i = tx + 32 * b;
-            if (i < m) {
-              rhs[0][i] -= H[a][b] * x0;
-              if (nv == 2) rhs[1][i] -= H[a][b] * x1;
-            }
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
 
   double tr = 0.0;
   for (int m = tid; m < s; m += 1024) {
-    const double x0 = rhs[0][m] / diag[m];
+    const double x0 = rhs[0][m];
     At[(int64_t)v0 * s + m] = x0;
     tr += x0 * x0;
     if (nv == 2) {
-      const double x1 = rhs[1][m] / diag[m];
+      const double x1 = rhs[1][m];
       At[(int64_t)v1 * s + m] = x1;
       tr += x1 * x1;
     }
   }
-  // deterministic block sum of the class's trace contribution
-  __shared__ double red[16];
   tr = wave_sum(tr);
   if (lane == 0) red[wave] = tr;
   __syncthreads();
@@ -188,15 +244,20 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
   }
 }
 
-hipError_t launch_solve_classes(const double* G, const double* B, const double* Q,
+hipError_t launch_solve_classes(const double* G, const double* B, const double* Qt,
                                 int32_t Ik, int32_t s, double lam, double delta, double rho,
                                 double* At, double* trace_part, hipStream_t st) {
   const int ncls = Ik / 2 + 1;
   const int sb = (s + 31) / 32;
+  // packed factor, or the projection partials before it exists
+  const size_t lds = (size_t)std::max(s * (s + 1) / 2, 1024) * sizeof(double);
   switch (sb) {
 #define FCTN_SOLVE_CASE(N)                                                                 \
   case N:                                                                                  \
-    solve_classes_k<N><<<ncls, 1024, 0, st>>>(G, B, Q, Ik, s, lam, delta, rho, At, trace_part); \
+    hipFuncSetAttribute((const void*)solve_classes_k<N>,                                   \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);             \
+    solve_classes_k<N><<<ncls, 1024, lds, st>>>(G, B, Qt, Ik, s, lam, delta, rho, At,    \
+                                                trace_part);                               \
     break;
     FCTN_SOLVE_CASE(1)
     FCTN_SOLVE_CASE(2)
@@ -211,31 +272,48 @@ hipError_t launch_solve_classes(const double* G, const double* B, const double* 
   return hipGetLastError();
 }
 
+// A = Q A~ on float64 MFMA: one 16x16 output tile per wave, k = i_k.
 template <typename W>
 __global__ void __launch_bounds__(256) backtransform_k(const double* __restrict__ Q,
                                                        const double* __restrict__ At, int Ik,
                                                        int s, int64_t spost,
                                                        double* __restrict__ A64,
                                                        W* __restrict__ Aw, W* __restrict__ Au) {
-  const int64_t total = (int64_t)Ik * s;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / s), j = (int)(e % s);
-    const double* q = Q + (int64_t)i * Ik;
-    double acc = 0.0;
-    for (int v = 0; v < Ik; ++v) acc += q[v] * At[(int64_t)v * s + j];
-    const int64_t f = (j / spost) * ((int64_t)Ik * spost) + (int64_t)i * spost + j % spost;
-    A64[f] = acc;
-    Aw[f] = (W)acc;
-    Au[e] = (W)acc;
+  typedef Mfma<double> MM;
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nbj = (s + 15) / 16, nbi = (Ik + 15) / 16;
+  if (t >= nbi * nbj) return;
+  const int i0 = (t / nbj) * 16, j0 = (t % nbj) * 16;
+  const int kr = lane >> 4, lc = lane & 15;
+  const int ia = i0 + lc, jb = j0 + lc;
+  typename MM::acc_t acc = MM::zero();
+  for (int k0 = 0; k0 < Ik; k0 += 4) {
+    const int k = k0 + kr;
+    const double a = (ia < Ik && k < Ik) ? Q[(int64_t)ia * Ik + k] : 0.0;
+    const double b = (k < Ik && jb < s) ? At[(int64_t)k * s + jb] : 0.0;
+    acc = MM::mma(a, b, acc);
+  }
+  if (jb < s) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + MM::row(lane, r);
+      if (i < Ik) {
+        const double v = acc[r];
+        const int64_t f = (jb / spost) * ((int64_t)Ik * spost) + (int64_t)i * spost + jb % spost;
+        A64[f] = v;
+        Aw[f] = (W)v;
+        Au[(int64_t)i * s + jb] = (W)v;
+      }
+    }
   }
 }
 
 hipError_t launch_backtransform(int prec, const double* Q, const double* At, int32_t Ik,
                                 int32_t s, int64_t spost, double* A64, void* Aw, void* Au,
                                 hipStream_t st) {
-  const int64_t total = (int64_t)Ik * s;
-  const int nb = (int)(cdiv(total, 256) < 2048 ? cdiv(total, 256) : 2048);
+  const int tiles = ((Ik + 15) / 16) * ((s + 15) / 16);
+  const int nb = (tiles + 3) / 4;
   if (prec == P_F64)
     backtransform_k<double><<<nb, 256, 0, st>>>(Q, At, Ik, s, spost, A64, (double*)Aw,
                                                 (double*)Au);

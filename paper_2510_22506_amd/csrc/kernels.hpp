@@ -24,16 +24,39 @@ struct XView {
   int32_t Ik;
 };
 
+// Column tile: a TCu x TCv block of (cu, cv) pairs; tile column
+// c = cu_l * TCv + cv_l.  Its block of M is generated on MFMA as the product
+//   O[p][q] = sum_kap Us[kap][p] Vs[kap][q],  p = cu_l * Ru + ru,  q = cv_l * Rv + rv
+// of the staged operand slabs, then scattered to M[ru * Rv + rv][c].
+// Slab element (kap, p) sits at kap * us_k + p * us_p (either order, chosen so
+// that the global reads are contiguous).
+struct TileGeom {
+  int32_t TCu, TCv, tcol, tcolp;  // tcolp: tcol rounded up to the MFMA k step
+  int32_t Pu, Qv, Pp, Qp, Kp;     // GEMM sizes, 16-padded, and K padded to 4
+  int32_t us_k, us_p, vs_k, vs_q; // slab strides
+  int32_t u_len, v_len;           // slab sizes (elements)
+  int64_t nTileU, nTileV, nColTiles;
+};
+
 // Launch geometry of the fused sub-network / Gram / right-hand-side pass.
 struct GramGeom {
+  TileGeom tg;
   int32_t s, sp, Ik, ip;     // sizes and 16-padded sizes
   int32_t nG, nB, nTiles;    // upper-triangle Gram tiles, RHS tiles, total
   int32_t nbj;               // 16-blocks along s
   int32_t tilesPerGroup, nGroups;
-  int32_t tc;                // columns per LDS tile
-  int64_t nColTiles, colTilesPerSplit;
+  int64_t colTilesPerSplit;
   int32_t nSplit;
   int32_t ldm, ldx, xrows;   // LDS leading dims and X rows held per group
+  size_t lds_bytes;
+};
+
+// Launch geometry of the reconstruction Z_(k) = A_k(k) M_k.
+struct RecGeom {
+  TileGeom tg;
+  int32_t s, sp, Ik, ip;
+  int32_t ldm, lda;          // Ms [tcolp][ldm]; staged A [ip][lda] (lda = 0: read from HBM)
+  int32_t nblk;
   size_t lds_bytes;
 };
 
@@ -54,20 +77,21 @@ hipError_t launch_init_observed(int prec, const void* Y, const uint8_t* mask, vo
                                 hipStream_t st);
 hipError_t launch_cast_factor(int prec, const double* A64, void* Aw, void* Au, int32_t Ik,
                               int32_t s, int64_t spost, hipStream_t st);
-hipError_t launch_build_basis(double* Q, double* lam_col, int32_t n, double delta, hipStream_t st);
+hipError_t launch_build_basis(double* Q, double* Qt, double* lam_col, int32_t n, double delta,
+                              hipStream_t st);
 hipError_t launch_pair(int prec, const PairDesc& pd, void* P, hipStream_t st);
 hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView& xv,
                            const GramGeom& g, void* part, hipStream_t st);
 hipError_t launch_reduce_gb(int prec, const GramGeom& g, const void* part, const double* A64,
                             int64_t spost, double rho, double* G, double* B, hipStream_t st);
-hipError_t launch_solve_classes(const double* G, const double* B, const double* Q,
+hipError_t launch_solve_classes(const double* G, const double* B, const double* Qt,
                                 int32_t Ik, int32_t s, double lam, double delta, double rho,
                                 double* At, double* trace_part, hipStream_t st);
 hipError_t launch_backtransform(int prec, const double* Q, const double* At, int32_t Ik,
                                 int32_t s, int64_t spost, double* A64, void* Aw, void* Au,
                                 hipStream_t st);
 hipError_t launch_reconstruct(int prec, const MGen& mg, const void* Au, void* Z,
-                              const XView& xv, int32_t s, int64_t C, hipStream_t st);
+                              const XView& xv, const RecGeom& g, hipStream_t st);
 hipError_t launch_x_update(int prec, void* X, const void* Z, const uint32_t* bits, double rho,
                            int64_t n, int nblk, double* xpart, hipStream_t st);
 hipError_t launch_stats(const double* xpart, int nblk, const double* trace_part,

@@ -55,6 +55,19 @@ class fctn_stats(ctypes.Structure):
                 ("objective", ctypes.c_double)]
 
 
+STAGES = ["pair", "gram_rhs", "reduce", "solve", "backtransform", "reconstruct", "x_update",
+          "stats"]
+
+
+class fctn_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8),
+                ("flops", ctypes.c_double * 8), ("bytes", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        return {name: {"launches": self.launches[i], "ms": self.ms[i], "flops": self.flops[i],
+                       "bytes": self.bytes[i]} for i, name in enumerate(STAGES)}
+
+
 _lib = None
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(fctn_desc)
@@ -78,6 +91,8 @@ _SIGS = {
     "fctn_step_x_update": (ctypes.c_int, [_P, _P, ctypes.POINTER(fctn_sweep_stats)]),
     "fctn_mode_sizes": (ctypes.c_int, [_D, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_int64)]),
+    "fctn_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "fctn_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(fctn_profile), ctypes.c_int32]),
     "fctn_destroy": (ctypes.c_int, [_P]),
     "fctn_status_str": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -262,6 +277,16 @@ class Plan:
         _check(lib().fctn_step_x_update(self.handle, _ptr(Z), ctypes.byref(st)),
                "fctn_step_x_update")
         return st.as_dict()
+
+    # -- per-kernel timing ---------------------------------------------------------
+    def profile_enable(self, on=True):
+        _check(lib().fctn_profile_enable(self.handle, int(bool(on))), "fctn_profile_enable")
+
+    def profile_read(self, reset=True):
+        out = fctn_profile()
+        _check(lib().fctn_profile_read(self.handle, ctypes.byref(out), int(bool(reset))),
+               "fctn_profile_read")
+        return out.as_dict()
 
     def close(self):
         if getattr(self, "handle", None):

@@ -80,3 +80,16 @@ def test_plan_rejects_bad_arguments_without_touching_the_device(F):
                          ctypes.byref(h)) == F.E_NOMEM
     assert lib.fctn_sweep(None, 1, None) == F.E_INVALID
     assert lib.fctn_destroy(None) == F.E_INVALID
+
+
+def test_every_small_shape_is_supported(F):
+    import itertools
+    bad = []
+    for dims in itertools.product([1, 2, 3, 5, 7, 16, 33], [1, 3, 4, 17], [1, 2, 3, 5]):
+        for p in ("f64", "f32"):
+            if F.fctn_workspace_bytes(F.make_desc(dims, (2, 3, 2), precision=p)) == 0:
+                bad.append((dims, p))
+    for dims in [(1, 1, 1, 1), (2, 3, 1, 2), (13, 11, 3, 7), (5, 3, 3, 2)]:
+        if F.fctn_workspace_bytes(F.make_desc(dims, (2,) * 6, precision="f32")) == 0:
+            bad.append(dims)
+    assert not bad

@@ -191,6 +191,23 @@ def test_sweeps_f32(name, dims, sweeps):
     np.testing.assert_array_equal(Xg[obs], prob.Y[obs])
 
 
+@pytest.mark.parametrize("dims,ranks", [((2, 5, 3), (2, 3, 2)), ((1, 6, 4), (1, 2, 3)),
+                                        ((5, 3, 3), (2, 2, 2)), ((3, 2, 1, 4), (2, 1, 2, 1, 2, 2))])
+def test_sweeps_degenerate_modes(dims, ranks):
+    # modes of size 1 and 2 (a single Fourier class, the n = 2 Laplacian) and
+    # tensors smaller than one tile
+    prob = make_problem("c1", seed=8, dims=(4, 4, 4), precision="f64", sr=0.5)
+    rng = np.random.default_rng(9)
+    prob.dims, prob.ranks = dims, ranks
+    prob.truth = rng.random(dims)
+    prob.mask = (rng.random(dims) < 0.5).astype(np.uint8)
+    prob.Y = np.where(prob.mask != 0, prob.truth, 0.0)
+    prob.A0 = init_factors(rng, dims, ranks)
+    p = _run_gpu(prob, "f64", 5, True, 1)
+    Xo, _, _ = _run_oracle(prob, "f64", 5, True, 1)
+    assert _rel(p.x().cpu().numpy(), Xo) <= TOL["f64"]
+
+
 def test_c1_full_reuse_on_and_off():
     prob = make_problem("c1", seed=0)
     for reuse in (True, False):
