@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
   __shared__ double red[16];
   extern __shared__ double Lp[];   // s (s + 1) / 2 packed lower factor
   const int c = blockIdx.x;
-  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   int nv = 2, v0 = 2 * c - 1, v1 = 2 * c;
   if (c == 0) {
@@ -70,113 +70,98 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
     }
   }
 
-  // H = G + sigma I (lower part), 32x32 cyclic: thread (ty, tx) holds rows
-  // ty + 32a and columns tx + 32b
+  // H = G + sigma I, 32x32 cyclic: thread (r, c) = (tid % 32, tid / 32) holds
+  // rows r + 32a and columns c + 32b (lower blocks b <= a only).  The 32
+  // holders of a column are one half-wave.  G is symmetric, so G[m][i] is read
+  // (consecutive lanes, consecutive addresses).
+  const int r = tid & 31, cc = tid >> 5;
   double H[SB][SB];
 #pragma unroll
   for (int a = 0; a < SB; ++a) {
-    const int i = ty + 32 * a;
+    const int i = r + 32 * a;
 #pragma unroll
-    for (int b = 0; b < SB; ++b) {
-      const int m = tx + 32 * b;
-      H[a][b] = (i < s && m <= i) ? G[(int64_t)i * s + m] + (i == m ? sigma : 0.0) : 0.0;
+    for (int b = 0; b <= a; ++b) {
+      const int m = cc + 32 * b;
+      H[a][b] = (i < s && m <= i) ? G[(int64_t)m * s + i] + (i == m ? sigma : 0.0) : 0.0;
     }
   }
   __syncthreads();
 
-  // right-looking Cholesky; the class right-hand sides ride along as extra
-  // rows kept in rhs[] (forward substitution): after column j their entries
-  // beyond j are updated with l_{rhs,j} l_{m,j}, l_{rhs,j} = rhs[v][j] / sqrt(d_j).
-  // Register blocks that are finished (all rows or columns <= j) or above
-  // the diagonal are skipped; both tests are uniform across a wave.
+  // right-looking Cholesky.  Per column j the half-wave holding it publishes
+  // the raw column to LDS and the pivot's holder publishes sqrt(d_j) and its
+  // reciprocal; after the barrier every thread forms its row and column
+  // multipliers (zero outside the trailing range, so the rank-1 update needs
+  // no per-element tests: strictly upper entries of diagonal blocks receive
+  // values that are never read) and updates its trailing blocks.  Finished
+  // blocks are skipped with wave-uniform tests.
   for (int j = 0; j < s; ++j) {
     const int jb = j >> 5, jt = j & 31;
     double* cb = colbuf[j & 1];
-    if (tx == jt) {
+    if (cc == jt) {
+      double pv = 1.0;
 #pragma unroll
       for (int a = 0; a < SB; ++a) {
-        const int i = ty + 32 * a;
-        if (a >= jb && i >= j && i < s) {
+        if (a < jb) continue;
+        double v = 0.0;
 #pragma unroll
-          for (int b = 0; b <= a; ++b)
-            if (b == jb) {
-              cb[i] = H[a][b];
-              if (i == j) {   // the one thread holding the pivot
-                const double sq = sqrt(H[a][b]);
-                diag[j] = sq;
-                rdiag[j] = 1.0 / sq;
-              }
-            }
-        }
+        for (int b = 0; b <= a; ++b)
+          if (b == jb) v = H[a][b];
+        const int i = r + 32 * a;
+        if (i >= j && i < s) cb[i] = v;
+        if (i == j) pv = v;
+      }
+      if (r == jt) {
+        const double sq = sqrt(pv);
+        diag[j] = sq;
+        rdiag[j] = 1.0 / sq;
       }
     }
     __syncthreads();
-    const double sd = diag[j];
     const double rs = rdiag[j];
-    double lm[SB];
+    double lm[SB], li[SB];
 #pragma unroll
     for (int b = 0; b < SB; ++b) {
-      const int m = tx + 32 * b;
-      lm[b] = (32 * b + 31 > j && m > j && m < s) ? cb[m] * rs : 0.0;
+      const int m = cc + 32 * b, i = r + 32 * b;
+      const bool act = 32 * b + 31 > j;
+      lm[b] = (act && m > j && m < s) ? cb[m] * rs : 0.0;
+      li[b] = (act && i > j && i < s) ? cb[i] * rs : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < SB; ++a) {
       if (32 * a + 31 <= j) continue;
-      const int i = ty + 32 * a;
-      if (i > j && i < s) {
-        const double li = cb[i] * rs;
 #pragma unroll
-        for (int b = 0; b <= a; ++b) {
-          if (32 * b + 31 <= j) continue;
-          const int m = tx + 32 * b;
-          if (m > j && m <= i) H[a][b] -= li * lm[b];
-        }
-      }
-    }
-    if (ty < nv) {
-      const double yj = rhs[ty][j] * rs;
-#pragma unroll
-      for (int b = 0; b < SB; ++b) {
+      for (int b = 0; b <= a; ++b) {
         if (32 * b + 31 <= j) continue;
-        const int m = tx + 32 * b;
-        if (m > j && m < s) rhs[ty][m] -= yj * lm[b];
+        H[a][b] -= li[a] * lm[b];
       }
     }
-    if (tx == jt) {
+    if (cc == jt) {
+      const double sd = diag[j];
 #pragma unroll
       for (int a = 0; a < SB; ++a) {
-        const int i = ty + 32 * a;
+        if (a < jb) continue;
+        const int i = r + 32 * a;
 #pragma unroll
-        for (int b = 0; b <= a; ++b) {
-          if (b == jb) {
-            if (i == j) H[a][b] = sd;
-            else if (i > j && i < s) H[a][b] = cb[i] * rs;
-          }
-        }
+        for (int b = 0; b <= a; ++b)
+          if (b == jb) H[a][b] = (i == j) ? sd : ((i > j && i < s) ? li[a] : H[a][b]);
       }
     }
   }
   // L to LDS (packed lower: row i starts at i (i + 1) / 2)
 #pragma unroll
   for (int a = 0; a < SB; ++a) {
-    const int i = ty + 32 * a;
+    const int i = r + 32 * a;
 #pragma unroll
     for (int b = 0; b <= a; ++b) {
-      const int m = tx + 32 * b;
+      const int m = cc + 32 * b;
       if (i < s && m <= i) Lp[i * (i + 1) / 2 + m] = H[a][b];
     }
   }
   __syncthreads();
-  // y = forward-substitution result
-  for (int m = tid; m < s; m += 1024) {
-    rhs[0][m] *= rdiag[m];
-    rhs[1][m] *= rdiag[m];
-  }
-  __syncthreads();
 
-  // back substitution L^T x = y in one wave, column-oriented: lane l keeps
-  // y_i for i = l + 64 q in registers; x_m is broadcast from its owner lane
-  // with readlane, then every lane removes L[m][i] x_m from its y_i (i < m)
+  // forward (L y = b~) and back (L^T x = y) substitution in one wave,
+  // column-oriented: lane l keeps entries i = l + 64 q in registers; the
+  // pivot entry is broadcast from its owner lane with readlane
   if (wave == 0) {
     constexpr int NQ = (32 * SB + 63) / 64;
     double y0[NQ], y1[NQ];
@@ -185,6 +170,31 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
       const int i = lane + 64 * q;
       y0[q] = i < s ? rhs[0][i] : 0.0;
       y1[q] = i < s ? rhs[1][i] : 0.0;
+    }
+    for (int m = 0; m < s; ++m) {
+      const int owner = m & 63, qm = m >> 6;
+      double ym0 = 0.0, ym1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q == qm) {
+          ym0 = y0[q];
+          ym1 = y1[q];
+        }
+      const double rd = rdiag[m];
+      const double x0 = bcast_lane(ym0, owner) * rd;
+      const double x1 = bcast_lane(ym1, owner) * rd;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int i = lane + 64 * q;
+        if (i > m && i < s) {
+          const double l = Lp[i * (i + 1) / 2 + m];
+          y0[q] -= l * x0;
+          y1[q] -= l * x1;
+        } else if (i == m) {
+          y0[q] = x0;
+          y1[q] = x1;
+        }
+      }
     }
     for (int m = s - 1; m >= 0; --m) {
       const int owner = m & 63, qm = m >> 6;
