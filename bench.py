@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="add the per-stage breakdown")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed region, copy 256 MiB device-to-device once (a "
+                         "kernel of known traffic for scaling HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -180,6 +183,13 @@ def main():
                               "us_per_launch": v["ms"] * 1e3 / max(v["launches"], 1),
                               "gflop": v["flops"] / 1e9}
                           for k, v in prof.items() if v["launches"]}
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_sweeps)
     print(json.dumps(line), flush=True)

@@ -81,7 +81,7 @@ typedef struct {
                                        (Algorithm 2's permuted order)        */
 } fctn_desc;
 
-/* Per-sweep scalars (Algorithm 1 stopping rule; Section 3.4 objective f). */
+/* Per-sweep scalars (Algorithm 1 stopping rule; Section 3.5 objective f). */
 typedef struct {
   double rel_change;   /* ||X^{t+1} - X^t||_F / ||X^t||_F                    */
   double f_data;       /* 1/2 ||X^{t+1} - FCTN(A^{t+1})||_F^2                 */

@@ -20,7 +20,7 @@ single steps:
                  eq. 8), plus the generalized fold (eq. 9).
 * ``pam``        Algorithm 1 (PAM-FCTNLR) and Algorithm 2 (PAM-AFCTNLR with
                  intermediate-tensor reuse), the X update (eq. 10), the
-                 stopping rule and the objective f (Section 3.4), with flop
+                 stopping rule and the objective f (Section 3.5), with flop
                  counters for the complexity tables (Tables 1-2).
 * ``metrics``    PSNR as defined in Section 4.
 

@@ -4,7 +4,7 @@ Section 3.1 prints L_k as the circulant with diagonal -2-delta and periodic
 off-diagonals +1.  That matrix is negative definite, which makes the model
 unbounded below (scale A_1 by c and A_2 by 1/c) and contradicts the
 convergence proof, which needs every eigenvalue of the Kronecker system to be
-at least rho (Section 3.4, condition 1).  The reading used throughout is the
+at least rho (Section 3.5, proof of condition 1).  The reading used throughout is the
 negation, L = (2 + delta) I - S - S^T with S the cyclic shift: positive
 definite, eigenvalues delta + 4 sin^2(pi j / n), and the "negative Laplacian"
 in the usual sense (minus the periodic second difference).  ``printed_matrix``

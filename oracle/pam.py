@@ -139,7 +139,7 @@ def sweep_order(N, t, order_policy):
 
 def objective(X, factors, lam, delta):
     """f = 1/2 ||X - FCTN(A)||^2 + sum_k lam_k/2 tr(A_k(k)^T L_k A_k(k))
-    (Section 3.4, f without the indicator, which is zero on feasible X)."""
+    (Section 3.5, f without the indicator, which is zero on feasible X)."""
     Z = tensor.fctn(factors)
     f = 0.5 * float(np.sum((X - Z) ** 2))
     for k, A in enumerate(factors):

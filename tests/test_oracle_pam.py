@@ -1,5 +1,5 @@
 """Pins for the oracle's PAM loop (Algorithms 1-2): exact block-decrease
-identities (Section 3.4, condition 4), monotone objective, observed entries
+identities (Section 3.5, condition 4), monotone objective, observed entries
 bit-exact, reuse on == reuse off, the Eckart-Young limit for N = 2, the
 stopping rule, and the per-sweep flop counts of Tables 1-2."""
 
