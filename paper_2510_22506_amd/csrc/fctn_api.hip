@@ -20,7 +20,6 @@ namespace {
 
 constexpr int kHist = 4096;
 constexpr int kXBlocks = 1024;
-constexpr int kTilesPerGroup = 64;      // 4 waves x 16 tiles
 constexpr int kTargetGramWGs = 512;
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -224,6 +223,11 @@ void setup_modes(fctn_plan_s* P) {
 }
 
 inline int ld_mod(int x, int r) { return x + ((r - x % 64) % 64 + 64) % 64; }
+inline int floor_log2(int x) {
+  int l = 0;
+  while ((2 << l) <= x) ++l;
+  return l;
+}
 
 // Operand slabs: [kap][p] (p contiguous; ld = 16 mod 64) unless kap is the
 // contiguous index in HBM, then [p][kap] (ld = 4 mod 64).  Both orders give
@@ -248,6 +252,9 @@ void fill_tile(const MGen& mg, int TCu, int TCv, TileGeom* tg) {
   } else {
     tg->vs_q = 1; tg->vs_k = ld_mod(tg->Qp, 16); tg->v_len = tg->Kp * tg->vs_k;
   }
+  // staging lanes along the slab's contiguous index (at most 64)
+  tg->u_lw = floor_log2(std::min(tg->us_k == 1 ? tg->Kp : tg->Pp, 64));
+  tg->v_lw = floor_log2(std::min(tg->vs_k == 1 ? tg->Kp : tg->Qp, 64));
   tg->nTileU = (mg.Cu + TCu - 1) / TCu;
   tg->nTileV = (mg.Cv + TCv - 1) / TCv;
   tg->nColTiles = tg->nTileU * tg->nTileV;
@@ -256,6 +263,11 @@ void fill_tile(const MGen& mg, int TCu, int TCv, TileGeom* tg) {
 // Pick the column tile minimizing MFMA instructions (padding included) per
 // real column, plus a fixed per-tile overhead, within the LDS budget.
 // extra_mfma(tg) is the consumer's work per tile; lds(tg) its LDS bytes.
+// rows of the index tables kept in LDS per launch
+inline size_t table_bytes(const TileGeom& tg, bool with_cols) {
+  return sizeof(SlabRow) * (size_t)(tg.Pp + tg.Qp + (with_cols ? tg.tcolp : 0));
+}
+
 template <class Extra, class Lds>
 bool choose_tile(const MGen& mg, int mg_repeat, Extra extra_mfma, Lds lds, TileGeom* best) {
   static const int cv_c[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20, 24, 25, 30, 32, 40, 48, 50, 64};
@@ -280,7 +292,13 @@ bool choose_tile(const MGen& mg, int mg_repeat, Extra extra_mfma, Lds lds, TileG
       if (bytes > (size_t)gram_max_lds_bytes()) continue;
       const double mgen = (double)(tg.Pp / 16) * (tg.Qp / 16) * (tg.Kp / 4) * mg_repeat;
       const double real = ((double)mg.Cu / tg.nTileU) * ((double)mg.Cv / tg.nTileV);
-      double cost = (mgen + extra_mfma(tg) + 24.0) / real;
+      // staging: the U slab is reloaded when the cu block changes, the V slab
+      // when the cv block changes (tiles run cv-block fastest); an element
+      // costs about 1/48 of an MFMA instruction
+      const double u_per_tile = (double)tg.Kp * tg.Pp / (double)tg.nTileV;
+      const double v_per_tile = tg.nTileV > 1 ? (double)tg.Kp * tg.Qp : 0.0;
+      const double stage = (u_per_tile + v_per_tile) * mg_repeat / 48.0;
+      double cost = (mgen + stage + extra_mfma(tg) + 24.0) / real;
       if (bytes > 80 * 1024) cost *= 1.15;   // one workgroup per CU
       const double par = (double)tg.nColTiles * mg_repeat;
       if (par < 512.0) cost *= 512.0 / std::max(par, 1.0);   // too few tiles to fill 256 CUs
@@ -304,11 +322,12 @@ bool setup_geom(ModeInfo& m, size_t es) {
   g.nG = g.nbj * (g.nbj + 1) / 2;
   g.nB = (g.ip / 16) * g.nbj;
   g.nTiles = g.nG + g.nB;
-  g.tilesPerGroup = kTilesPerGroup;
-  g.nGroups = (g.nTiles + kTilesPerGroup - 1) / kTilesPerGroup;
+  const int tpg = gram_tiles_per_group();
+  g.tilesPerGroup = tpg;
+  g.nGroups = (g.nTiles + tpg - 1) / tpg;
   int xmax = 0;
   for (int grp = 0; grp < g.nGroups; ++grp) {
-    const int t0 = grp * kTilesPerGroup, t1 = std::min(t0 + kTilesPerGroup, g.nTiles);
+    const int t0 = grp * tpg, t1 = std::min(t0 + tpg, g.nTiles);
     if (t1 > g.nG) {
       const int bf = (std::max(t0, g.nG) - g.nG) / g.nbj, bl = (t1 - 1 - g.nG) / g.nbj;
       xmax = std::max(xmax, (bl - bf + 1) * 16);
@@ -318,7 +337,8 @@ bool setup_geom(ModeInfo& m, size_t es) {
   g.ldm = ld_pad(g.sp);
   g.ldx = ld_pad(std::max(xmax, 16));
   auto gram_lds = [&](const TileGeom& tg) {
-    return (size_t)(tg.u_len + tg.v_len + (size_t)tg.tcolp * (g.ldm + g.ldx)) * es;
+    return (size_t)(tg.u_len + tg.v_len + (size_t)tg.tcolp * (g.ldm + g.ldx)) * es +
+           table_bytes(tg, true);
   };
   auto gram_work = [&](const TileGeom& tg) { return (double)g.nTiles * (tg.tcolp / 4); };
   if (!choose_tile(m.mg, g.nGroups, gram_work, gram_lds, &g.tg)) return false;
@@ -338,7 +358,8 @@ bool setup_geom(ModeInfo& m, size_t es) {
   r.lda = stage_a ? lda : 0;
   auto rec_lds = [&](const TileGeom& tg) {
     const int ldm = ld_mod(std::max(r.sp, 4), 4);
-    return (size_t)(tg.u_len + tg.v_len + (size_t)tg.tcolp * ldm + (size_t)r.ip * r.lda) * es;
+    return (size_t)(tg.u_len + tg.v_len + (size_t)pad16(tg.tcolp) * ldm + (size_t)r.ip * r.lda) *
+               es + table_bytes(tg, false);
   };
   auto rec_work = [&](const TileGeom& tg) {
     return (double)(r.ip / 16) * (pad16(tg.tcolp) / 16) * (r.sp / 4);
@@ -410,6 +431,10 @@ bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
     P->fnum[k] = n;
   }
   setup_modes(P);
+  // the kernels index X, the factors and the pair tensors with 32-bit offsets
+  if (P->numel >= ((int64_t)1 << 31)) return false;
+  for (int p = 0; p < 2; ++p)
+    if (P->pnum[p] >= ((int64_t)1 << 31)) return false;
   for (int k = 0; k < P->N; ++k) {
     if (!solve_supported((int32_t)P->mode[k].s)) return false;
     if (!setup_geom(P->mode[k], P->es)) return false;

@@ -14,8 +14,9 @@
 
 namespace fctn {
 
-constexpr int kGramThreads = 256;
-constexpr int kTPW = 16;   // output tiles per wave
+constexpr int kGramThreads = 512;   // 8 waves
+constexpr int kGramWaves = kGramThreads / 64;
+constexpr int kTPW = 16;            // output tiles per wave
 
 __device__ inline void upper_tile(int t, int& bi, int& bj) {
   int j = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
@@ -25,48 +26,80 @@ __device__ inline void upper_tile(int t, int& bi, int& bj) {
   bi = t - j * (j + 1) / 2;
 }
 
-// Stage the operand slabs of column tile (cu0, cv0): Us(kap, p) = U[ru, cu, kap]
-// with p = cu_l * Ru + ru, Vs(kap, q) = V[rv, cv, kap] with q = cv_l * Rv + rv;
-// zero outside the tensor and in the padding.
-template <typename T>
-__device__ inline void stage_slabs(const MGen& mg, const TileGeom& tg, const T* __restrict__ U,
-                                   const T* __restrict__ V, int64_t cu0, int64_t cv0,
-                                   T* __restrict__ Us, T* __restrict__ Vs, int tid, int nth) {
-  // U slab: iterate kap fastest when the slab is [p][kap] (kap contiguous in HBM)
-  const bool u_kfast = tg.us_k == 1;
-  const int nu = tg.Kp * tg.Pp;
-  for (int e = tid; e < nu; e += nth) {
-    int k, p;
-    if (u_kfast) { p = e / tg.Kp; k = e - p * tg.Kp; }
-    else { k = e / tg.Pp; p = e - k * tg.Pp; }
-    T v = T(0);
-    if (k < mg.K && p < tg.Pu) {
+// Index tables of the tile's slabs and columns (once per launch).
+//   rows p of the U slab: off = ru u_ru + cu_l u_cu, map = cu_l TCv ldm + ru Rv
+//   rows q of the V slab: off = rv v_rv + cv_l v_cv, map = cv_l ldm + rv
+//   columns c of the tile: off = cu_l x_cu + cv_l x_cv (X view), cl = cu_l, map = cv_l
+__device__ inline void build_tables(const MGen& mg, const TileGeom& tg, const XView* xv, int ldm,
+                                    SlabRow* pt, SlabRow* qt, SlabRow* ct, int tid, int nth) {
+  for (int p = tid; p < tg.Pp; p += nth) {
+    SlabRow r{0, 1 << 30, -1, 0};
+    if (p < tg.Pu) {
       const int cul = p / mg.Ru, ru = p - cul * mg.Ru;
-      const int64_t cu = cu0 + cul;
-      if (cu < mg.Cu) v = U[ru * mg.u_ru + cu * mg.u_cu + (int64_t)k * mg.u_k];
+      r.off = (int32_t)(ru * mg.u_ru + cul * mg.u_cu);
+      r.cl = cul;
+      r.map = cul * tg.TCv * ldm + ru * mg.Rv;
     }
-    Us[k * tg.us_k + p * tg.us_p] = v;
+    pt[p] = r;
   }
-  const bool v_kfast = tg.vs_k == 1;
-  const int nv = tg.Kp * tg.Qp;
-  for (int e = tid; e < nv; e += nth) {
-    int k, q;
-    if (v_kfast) { q = e / tg.Kp; k = e - q * tg.Kp; }
-    else { k = e / tg.Qp; q = e - k * tg.Qp; }
-    T v = T(0);
-    if (k < mg.K && q < tg.Qv) {
+  for (int q = tid; q < tg.Qp; q += nth) {
+    SlabRow r{0, 1 << 30, -1, 0};
+    if (q < tg.Qv) {
       const int cvl = q / mg.Rv, rv = q - cvl * mg.Rv;
-      const int64_t cv = cv0 + cvl;
-      if (cv < mg.Cv) v = V[rv * mg.v_rv + cv * mg.v_cv + (int64_t)k * mg.v_k];
+      r.off = (int32_t)(rv * mg.v_rv + cvl * mg.v_cv);
+      r.cl = cvl;
+      r.map = cvl * ldm + rv;
     }
-    Vs[k * tg.vs_k + q * tg.vs_q] = v;
+    qt[q] = r;
+  }
+  if (xv) {
+    for (int c = tid; c < tg.tcolp; c += nth) {
+      SlabRow r{0, 1 << 30, 1 << 30, 0};
+      if (c < tg.tcol) {
+        const int cul = c / tg.TCv, cvl = c - cul * tg.TCv;
+        r.off = (int32_t)(cul * xv->x_cu + cvl * xv->x_cv);
+        r.cl = cul;
+        r.map = cvl;
+      }
+      ct[c] = r;
+    }
   }
 }
 
-// M block of the tile on MFMA, scattered to Ms[c * ldm + row].
+// Stage one operand slab S(kap, p) = F[tab[p].off + base + kap * f_k] (zero
+// in the padding and beyond the tensor edge: tab[p].cl >= lim).  Lanes run
+// along the slab's contiguous index (2^lw of them).
 template <typename T>
-__device__ inline void mgen_mfma(const MGen& mg, const TileGeom& tg, const T* __restrict__ Us,
-                                 const T* __restrict__ Vs, T* __restrict__ Ms, int ldm, int lane,
+__device__ inline void stage_slab(const T* __restrict__ F, int64_t base, int64_t f_k, int K,
+                                  int Kp, int Pp, int s_k, int s_p, int lw,
+                                  const SlabRow* __restrict__ tab, int64_t lim,
+                                  T* __restrict__ S, int tid, int nth) {
+  const int lanes = 1 << lw, lane = tid & (lanes - 1), grp = tid >> lw, ngrp = nth >> lw;
+  if (s_k == 1) {                       // [p][kap]: lanes along kap
+    for (int p = grp; p < Pp; p += ngrp) {
+      const SlabRow r = tab[p];
+      const bool okp = r.cl < lim;
+      const T* src = F + base + r.off;
+      for (int k = lane; k < Kp; k += lanes)
+        S[p * s_p + k] = (okp && k < K) ? src[(int64_t)k * f_k] : T(0);
+    }
+  } else {                              // [kap][p]: lanes along p
+    for (int k = grp; k < Kp; k += ngrp) {
+      const bool okk = k < K;
+      for (int p = lane; p < Pp; p += lanes) {
+        const SlabRow r = tab[p];
+        S[k * s_k + p] = (okk && r.cl < lim) ? F[base + r.off + (int64_t)k * f_k] : T(0);
+      }
+    }
+  }
+}
+
+// The tile's block of M on MFMA: O[p][q] = sum_kap Us(kap, p) Vs(kap, q),
+// scattered to Ms[pt[p].map + qt[q].map].
+template <typename T>
+__device__ inline void mgen_mfma(const TileGeom& tg, const T* __restrict__ Us,
+                                 const T* __restrict__ Vs, const SlabRow* __restrict__ ptab,
+                                 const SlabRow* __restrict__ qtab, T* __restrict__ Ms, int lane,
                                  int wave, int nwaves) {
   typedef Mfma<T> MM;
   const int npt = tg.Pp / 16, nqt = tg.Qp / 16;
@@ -81,18 +114,33 @@ __device__ inline void mgen_mfma(const MGen& mg, const TileGeom& tg, const T* __
       const T b = vb[(k0 + kr) * tg.vs_k];
       acc = MM::mma(a, b, acc);
     }
-    const int q = qt * 16 + lc;
-    if (q < tg.Qv) {
-      const int cvl = q / mg.Rv, rv = q - cvl * mg.Rv;
+    const int qm = qtab[qt * 16 + lc].map;
+    if (qm >= 0) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int p = pt * 16 + MM::row(lane, i);
-        if (p < tg.Pu) {
-          const int cul = p / mg.Ru, ru = p - cul * mg.Ru;
-          Ms[(cul * tg.TCv + cvl) * ldm + ru * mg.Rv + rv] = acc[i];
-        }
+        const int pm = ptab[pt * 16 + MM::row(lane, i)].map;
+        if (pm >= 0) Ms[pm + qm] = acc[i];
       }
     }
+  }
+}
+
+template <typename T>
+__device__ inline void stage_operands(const MGen& mg, const TileGeom& tg, const T* U, const T* V,
+                                      int64_t tu, int64_t tv, int64_t& cur_tu, int64_t& cur_tv,
+                                      T* Us, T* Vs, const SlabRow* ptab, const SlabRow* qtab,
+                                      int tid, int nth) {
+  if (tu != cur_tu) {
+    const int64_t cu0 = tu * tg.TCu;
+    stage_slab<T>(U, cu0 * mg.u_cu, mg.u_k, mg.K, tg.Kp, tg.Pp, tg.us_k, tg.us_p, tg.u_lw, ptab,
+                  mg.Cu - cu0, Us, tid, nth);
+    cur_tu = tu;
+  }
+  if (tv != cur_tv) {
+    const int64_t cv0 = tv * tg.TCv;
+    stage_slab<T>(V, cv0 * mg.v_cv, mg.v_k, mg.K, tg.Kp, tg.Qp, tg.vs_k, tg.vs_q, tg.v_lw, qtab,
+                  mg.Cv - cv0, Vs, tid, nth);
+    cur_tv = tv;
   }
 }
 
@@ -103,7 +151,10 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
   typedef Mfma<T> MM;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileGeom& tg = g.tg;
-  T* Us = (T*)smem_raw;
+  SlabRow* ptab = (SlabRow*)smem_raw;
+  SlabRow* qtab = ptab + tg.Pp;
+  SlabRow* ctab = qtab + tg.Qp;
+  T* Us = (T*)(ctab + tg.tcolp);
   T* Vs = Us + tg.u_len;
   T* Ms = Vs + tg.v_len;                        // [tcolp][ldm]  rows of M fastest
   T* Xs = Ms + (int64_t)tg.tcolp * g.ldm;       // [tcolp][ldx]  rows of X_(k) fastest
@@ -128,7 +179,7 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
   typename MM::acc_t acc[kTPW];
 #pragma unroll
   for (int j = 0; j < kTPW; ++j) {
-    const int t = t0 + wave + 4 * j;
+    const int t = t0 + wave + kGramWaves * j;
     valid[j] = t < t1;
     acc[j] = MM::zero();
     int bi = 0, bj = 0;
@@ -147,6 +198,7 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
     boff[j] = bj * 16 + (lane & 15);
   }
 
+  build_tables(mg, tg, &xv, g.ldm, ptab, qtab, ctab, tid, kGramThreads);
   // rows of M beyond s and columns beyond the tile (in M and X) stay zero for
   // the whole launch: uninitialized LDS could hold NaN patterns, and NaN * 0
   // would poison the products
@@ -157,36 +209,39 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
   const int64_t ct0 = (int64_t)split * g.colTilesPerSplit;
   const int64_t ct1 = min(ct0 + g.colTilesPerSplit, tg.nColTiles);
   const int ldm = g.ldm, ldx = g.ldx;
+  int64_t cur_tu = -1, cur_tv = -1;
+  // X staging: lanes along the contiguous index of the X view
+  const bool x_rfast = xv.x_ik == 1;
+  const int xl = x_rfast ? min(xrows, 16) : 16;   // xrows is a multiple of 16
 
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
-    const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
-    stage_slabs<T>(mg, tg, U, V, cu0, cv0, Us, Vs, tid, kGramThreads);
+    stage_operands<T>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
+                      kGramThreads);
     if (xrows > 0) {
-      const int ne = tg.tcol * xrows;
-      for (int e = tid; e < ne; e += kGramThreads) {
-        int cul, cvl, r;
-        if (xv.x_ik == 1) {
-          r = e % xrows;
-          const int c = e / xrows;
-          cul = c / tg.TCv;
-          cvl = c - cul * tg.TCv;
-        } else {
-          cvl = e % tg.TCv;
-          const int rest = e / tg.TCv;
-          cul = rest % tg.TCu;
-          r = rest / tg.TCu;
+      const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
+      const int64_t lim_u = mg.Cu - cu0, lim_v = mg.Cv - cv0;
+      const T* xb = X + cu0 * xv.x_cu + cv0 * xv.x_cv + (int64_t)(ba_lo * 16) * xv.x_ik;
+      const int xlim = xv.Ik - ba_lo * 16;
+      if (x_rfast) {
+        const int l = tid % xl, grp = tid / xl, ngrp = kGramThreads / xl;
+        for (int c = grp; c < tg.tcol; c += ngrp) {
+          const SlabRow cr = ctab[c];
+          const bool okc = cr.cl < lim_u && cr.map < lim_v;
+          for (int r = l; r < xrows; r += xl)
+            Xs[c * ldx + r] = (okc && r < xlim) ? xb[cr.off + (int64_t)r * xv.x_ik] : T(0);
         }
-        const int ik = ba_lo * 16 + r;
-        const int64_t cu = cu0 + cul, cv = cv0 + cvl;
-        T v = T(0);
-        if (ik < xv.Ik && cu < mg.Cu && cv < mg.Cv)
-          v = X[cu * xv.x_cu + cv * xv.x_cv + (int64_t)ik * xv.x_ik];
-        Xs[(cul * tg.TCv + cvl) * ldx + r] = v;
+      } else {
+        for (int e = tid; e < tg.tcol * xrows; e += kGramThreads) {
+          const int r = e / tg.tcol, c = e - r * tg.tcol;
+          const SlabRow cr = ctab[c];
+          Xs[c * ldx + r] = (cr.cl < lim_u && cr.map < lim_v && r < xlim)
+                                ? xb[cr.off + (int64_t)r * xv.x_ik] : T(0);
+        }
       }
     }
     __syncthreads();
-    mgen_mfma<T>(mg, tg, Us, Vs, Ms, ldm, lane, wave, 4);
+    mgen_mfma<T>(tg, Us, Vs, ptab, qtab, Ms, lane, wave, kGramWaves);
     __syncthreads();
     const int kr = lane >> 4;
 #pragma unroll
@@ -207,13 +262,16 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
 #pragma unroll
   for (int j = 0; j < kTPW; ++j) {
     if (valid[j]) {
-      const int t = t0 + wave + 4 * j;
+      const int t = t0 + wave + kGramWaves * j;
       T* base = part + ((int64_t)split * g.nTiles + t) * 256;
 #pragma unroll
       for (int i = 0; i < 4; ++i) base[MM::row(lane, i) * 16 + (lane & 15)] = acc[j][i];
     }
   }
 }
+
+int gram_threads() { return kGramThreads; }
+int gram_tiles_per_group() { return kGramWaves * kTPW; }
 
 int gram_max_lds_bytes() { return 160 * 1024; }
 
@@ -296,7 +354,8 @@ hipError_t launch_reduce_gb(int prec, const GramGeom& g, const void* part, const
 // Z_(k) = A_k(k) M_k: per column tile the block of M_k is generated on MFMA
 // into LDS (the same generator as above), then Z's 16x16 tiles
 // (i_k block x column block) accumulate on MFMA over the s_k rows.  A_k(k) is
-// staged in LDS when it fits.  Z is written through the X view.
+// staged in LDS when it fits.  Each workgroup walks a contiguous range of
+// column tiles so that operand slabs are reused.  Z is written through the X view.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) reconstruct_k(MGen mg, const T* __restrict__ Au,
@@ -304,7 +363,9 @@ __global__ void __launch_bounds__(256) reconstruct_k(MGen mg, const T* __restric
   typedef Mfma<T> MM;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileGeom& tg = g.tg;
-  T* Us = (T*)smem_raw;
+  SlabRow* ptab = (SlabRow*)smem_raw;
+  SlabRow* qtab = ptab + tg.Pp;
+  T* Us = (T*)(qtab + tg.Qp);
   T* Vs = Us + tg.u_len;
   T* Ms = Vs + tg.v_len;                      // [tcolp][ldm]
   T* As = Ms + (int64_t)tg.tcolp * g.ldm;     // [ip][lda] when staged
@@ -313,6 +374,7 @@ __global__ void __launch_bounds__(256) reconstruct_k(MGen mg, const T* __restric
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kr = lane >> 4, lc = lane & 15;
 
+  build_tables(mg, tg, nullptr, g.ldm, ptab, qtab, nullptr, tid, 256);
   for (int e = tid; e < tg.tcolp * g.ldm; e += 256) Ms[e] = T(0);
   if (g.lda > 0) {
     for (int e = tid; e < g.ip * g.sp; e += 256) {
@@ -323,12 +385,15 @@ __global__ void __launch_bounds__(256) reconstruct_k(MGen mg, const T* __restric
   __syncthreads();
 
   const int nib = g.ip / 16, ncb = tg.tcolp / 16;
-  for (int64_t ct = blockIdx.x; ct < tg.nColTiles; ct += gridDim.x) {
+  const int64_t per = (tg.nColTiles + gridDim.x - 1) / gridDim.x;
+  const int64_t ct0 = (int64_t)blockIdx.x * per, ct1 = min(ct0 + per, tg.nColTiles);
+  int64_t cur_tu = -1, cur_tv = -1;
+  for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
     const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
-    stage_slabs<T>(mg, tg, U, V, cu0, cv0, Us, Vs, tid, 256);
+    stage_operands<T>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid, 256);
     __syncthreads();
-    mgen_mfma<T>(mg, tg, Us, Vs, Ms, g.ldm, lane, wave, 4);
+    mgen_mfma<T>(tg, Us, Vs, ptab, qtab, Ms, lane, wave, 4);
     __syncthreads();
     for (int t = wave; t < nib * ncb; t += 4) {
       const int ib = t / ncb, cb = t - (t / ncb) * ncb;

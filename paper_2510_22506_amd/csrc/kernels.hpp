@@ -35,7 +35,18 @@ struct TileGeom {
   int32_t Pu, Qv, Pp, Qp, Kp;     // GEMM sizes, 16-padded, and K padded to 4
   int32_t us_k, us_p, vs_k, vs_q; // slab strides
   int32_t u_len, v_len;           // slab sizes (elements)
+  int32_t u_lw, v_lw;             // log2 of the lanes that run along a slab's
+                                  // contiguous index when staging it
   int64_t nTileU, nTileV, nColTiles;
+};
+
+// Per-row / per-column index tables built once per launch in LDS so that the
+// staging and scatter loops need no integer division.
+struct SlabRow {        // row p = cu_l * Ru + ru of the U slab (or q of V)
+  int32_t off;          // ru * u_ru + cu_l * u_cu (element offset in U)
+  int32_t cl;           // cu_l (>= 2^30 for padding rows)
+  int32_t map;          // cu_l * TCv * ldm + ru * Rv (its part of the M index), -1 if padding
+  int32_t pad;
 };
 
 // Launch geometry of the fused sub-network / Gram / right-hand-side pass.
@@ -99,6 +110,8 @@ hipError_t launch_stats(const double* xpart, int nblk, const double* trace_part,
                         double* hist_slot, hipStream_t st);
 
 int gram_max_lds_bytes();
+int gram_threads();
+int gram_tiles_per_group();
 int solve_supported(int32_t s);
 
 }  // namespace fctn
