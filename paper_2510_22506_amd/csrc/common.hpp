@@ -75,6 +75,15 @@ __device__ inline double bcast_lane(double v, int src) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// 1/sqrt(d) for d > 0: hardware estimate refined by two Newton steps
+// (quadratic convergence to full double precision).
+__device__ inline double rsqrt_f64(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * (1.5 - 0.5 * d * y * y);
+  y = y * (1.5 - 0.5 * d * y * y);
+  return y;
+}
+
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace fctn

@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
                                                         int s, double lam, double delta,
                                                         double rho, double* __restrict__ At,
                                                         double* __restrict__ trace_part) {
-  __shared__ double colbuf[2][32 * SB];
+  __shared__ double colbuf[2][2][32 * SB];
   __shared__ double rhs[2][32 * SB];
   __shared__ double diag[32 * SB];
   __shared__ double rdiag[32 * SB];
@@ -87,63 +87,105 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
   }
   __syncthreads();
 
-  // right-looking Cholesky.  Per column j the half-wave holding it publishes
-  // the raw column to LDS and the pivot's holder publishes sqrt(d_j) and its
-  // reciprocal; after the barrier every thread forms its row and column
-  // multipliers (zero outside the trailing range, so the rank-1 update needs
-  // no per-element tests: strictly upper entries of diagonal blocks receive
-  // values that are never read) and updates its trailing blocks.  Finished
-  // blocks are skipped with wave-uniform tests.
-  for (int j = 0; j < s; ++j) {
+  // Right-looking Cholesky, two columns per barrier.  Columns j (even) and
+  // j + 1 are held by the two halves of one wave (lanes 0-31: column j, rows
+  // r + 32a; lanes 32-63: column j + 1).  That wave factors both without a
+  // workgroup barrier: pivot j by readlane, column j scaled and published to
+  // LDS, column j + 1 updated from it (same wave, in-order LDS), pivot j + 1,
+  // column j + 1 published.  After the barrier every thread applies the
+  // rank-2 update to its trailing blocks.  Multipliers outside the trailing
+  // range are zero, so the update needs no per-element tests (strictly upper
+  // entries of diagonal blocks receive values that are never read).
+  for (int j = 0; j < s; j += 2) {
     const int jb = j >> 5, jt = j & 31;
-    double* cb = colbuf[j & 1];
-    if (cc == jt) {
-      double pv = 1.0;
+    const bool two = j + 1 < s;
+    const int jlast = two ? j + 1 : j;
+    double* cb0 = colbuf[(j >> 1) & 1][0];
+    double* cb1 = colbuf[(j >> 1) & 1][1];
+    if (wave == (jt >> 1)) {
+      const int half = lane >> 5;
+      // this lane's column (j or j + 1), raw
+      double v[SB];
 #pragma unroll
       for (int a = 0; a < SB; ++a) {
-        if (a < jb) continue;
-        double v = 0.0;
+        v[a] = 0.0;
 #pragma unroll
         for (int b = 0; b <= a; ++b)
-          if (b == jb) v = H[a][b];
-        const int i = r + 32 * a;
-        if (i >= j && i < s) cb[i] = v;
-        if (i == j) pv = v;
+          if (b == jb) v[a] = H[a][b];
       }
-      if (r == jt) {
-        const double sq = sqrt(pv);
-        diag[j] = sq;
-        rdiag[j] = 1.0 / sq;
+      double vj = 0.0;
+#pragma unroll
+      for (int a = 0; a < SB; ++a)
+        if (a == jb) vj = v[a];
+      const double d0 = bcast_lane(vj, jt);
+      const double rs0 = rsqrt_f64(d0);
+      const double sd0 = d0 * rs0;
+#pragma unroll
+      for (int a = 0; a < SB; ++a) {
+        const int i = r + 32 * a;
+        if (half == 0 && i > j && i < s) cb0[i] = v[a] * rs0;
+      }
+      double rs1 = 0.0, sd1 = 0.0;
+      if (two) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const double l10 = cb0[j + 1];
+#pragma unroll
+        for (int a = 0; a < SB; ++a) {
+          const int i = r + 32 * a;
+          if (half == 1 && i > j && i < s) v[a] -= cb0[i] * l10;
+        }
+        double vj1 = 0.0;
+#pragma unroll
+        for (int a = 0; a < SB; ++a)
+          if (a == jb) vj1 = v[a];
+        const double d1 = bcast_lane(vj1, 32 + jt + 1);
+        rs1 = rsqrt_f64(d1);
+        sd1 = d1 * rs1;
+#pragma unroll
+        for (int a = 0; a < SB; ++a) {
+          const int i = r + 32 * a;
+          if (half == 1 && i > j + 1 && i < s) cb1[i] = v[a] * rs1;
+        }
+      }
+      // the owning lanes keep their finished column of L
+      const int jc = j + half;
+      const double rsc = half ? rs1 : rs0, sdc = half ? sd1 : sd0;
+#pragma unroll
+      for (int a = 0; a < SB; ++a) {
+        const int i = r + 32 * a;
+#pragma unroll
+        for (int b = 0; b <= a; ++b)
+          if (b == jb && jc < s) H[a][b] = (i == jc) ? sdc : ((i > jc && i < s) ? v[a] * rsc : H[a][b]);
+      }
+      if (lane == 0) {
+        diag[j] = sd0;
+        rdiag[j] = rs0;
+        if (two) {
+          diag[j + 1] = sd1;
+          rdiag[j + 1] = rs1;
+        }
       }
     }
     __syncthreads();
-    const double rs = rdiag[j];
-    double lm[SB], li[SB];
+    double lm0[SB], lm1[SB], li0[SB], li1[SB];
 #pragma unroll
     for (int b = 0; b < SB; ++b) {
       const int m = cc + 32 * b, i = r + 32 * b;
-      const bool act = 32 * b + 31 > j;
-      lm[b] = (act && m > j && m < s) ? cb[m] * rs : 0.0;
-      li[b] = (act && i > j && i < s) ? cb[i] * rs : 0.0;
+      const bool act = 32 * b + 31 > jlast;
+      const bool okm = act && m > jlast && m < s, oki = act && i > jlast && i < s;
+      lm0[b] = okm ? cb0[m] : 0.0;
+      li0[b] = oki ? cb0[i] : 0.0;
+      lm1[b] = (two && okm) ? cb1[m] : 0.0;
+      li1[b] = (two && oki) ? cb1[i] : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < SB; ++a) {
-      if (32 * a + 31 <= j) continue;
+      if (32 * a + 31 <= jlast) continue;
 #pragma unroll
       for (int b = 0; b <= a; ++b) {
-        if (32 * b + 31 <= j) continue;
-        H[a][b] -= li[a] * lm[b];
-      }
-    }
-    if (cc == jt) {
-      const double sd = diag[j];
-#pragma unroll
-      for (int a = 0; a < SB; ++a) {
-        if (a < jb) continue;
-        const int i = r + 32 * a;
-#pragma unroll
-        for (int b = 0; b <= a; ++b)
-          if (b == jb) H[a][b] = (i == j) ? sd : ((i > j && i < s) ? li[a] : H[a][b]);
+        if (32 * b + 31 <= jlast) continue;
+        H[a][b] -= li0[a] * lm0[b] + li1[a] * lm1[b];
       }
     }
   }
@@ -161,17 +203,36 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
 
   // forward (L y = b~) and back (L^T x = y) substitution in one wave,
   // column-oriented: lane l keeps entries i = l + 64 q in registers; the
-  // pivot entry is broadcast from its owner lane with readlane
+  // pivot entry is broadcast from its owner lane with readlane.  The next
+  // step's column (row) of L and its reciprocal pivot are loaded while the
+  // current step's updates run.
   if (wave == 0) {
     constexpr int NQ = (32 * SB + 63) / 64;
     double y0[NQ], y1[NQ];
+    int rowbase[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int i = lane + 64 * q;
       y0[q] = i < s ? rhs[0][i] : 0.0;
       y1[q] = i < s ? rhs[1][i] : 0.0;
+      rowbase[q] = i * (i + 1) / 2;
     }
+    // forward: column m of L is Lp[rowbase(i) + m] for i > m
+    double lc[NQ], ln[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + 64 * q;
+      lc[q] = (i > 0 && i < s) ? Lp[rowbase[q]] : 0.0;
+    }
+    double rdc = rdiag[0];
     for (int m = 0; m < s; ++m) {
+      const int mn = m + 1;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int i = lane + 64 * q;
+        ln[q] = (mn < s && i > mn && i < s) ? Lp[rowbase[q] + mn] : 0.0;
+      }
+      const double rdn = mn < s ? rdiag[mn] : 0.0;
       const int owner = m & 63, qm = m >> 6;
       double ym0 = 0.0, ym1 = 0.0;
 #pragma unroll
@@ -180,23 +241,38 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
           ym0 = y0[q];
           ym1 = y1[q];
         }
-      const double rd = rdiag[m];
-      const double x0 = bcast_lane(ym0, owner) * rd;
-      const double x1 = bcast_lane(ym1, owner) * rd;
+      const double x0 = bcast_lane(ym0, owner) * rdc;
+      const double x1 = bcast_lane(ym1, owner) * rdc;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int i = lane + 64 * q;
-        if (i > m && i < s) {
-          const double l = Lp[i * (i + 1) / 2 + m];
-          y0[q] -= l * x0;
-          y1[q] -= l * x1;
-        } else if (i == m) {
+        if (i == m) {
           y0[q] = x0;
           y1[q] = x1;
+        } else {
+          y0[q] -= lc[q] * x0;
+          y1[q] -= lc[q] * x1;
         }
+        lc[q] = ln[q];
       }
+      rdc = rdn;
     }
-    for (int m = s - 1; m >= 0; --m) {
+    // back: row m of L is Lp[m (m + 1) / 2 + i] for i < m
+    const int ms = s - 1;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + 64 * q;
+      lc[q] = (i < ms) ? Lp[ms * (ms + 1) / 2 + i] : 0.0;
+    }
+    rdc = rdiag[ms];
+    for (int m = ms; m >= 0; --m) {
+      const int mn = m - 1;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int i = lane + 64 * q;
+        ln[q] = (mn >= 0 && i < mn) ? Lp[mn * (mn + 1) / 2 + i] : 0.0;
+      }
+      const double rdn = mn >= 0 ? rdiag[mn] : 0.0;
       const int owner = m & 63, qm = m >> 6;
       double ym0 = 0.0, ym1 = 0.0;
 #pragma unroll
@@ -205,22 +281,21 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
           ym0 = y0[q];
           ym1 = y1[q];
         }
-      const double rd = rdiag[m];
-      const double x0 = bcast_lane(ym0, owner) * rd;
-      const double x1 = bcast_lane(ym1, owner) * rd;
-      const double* Lrow = Lp + m * (m + 1) / 2;
+      const double x0 = bcast_lane(ym0, owner) * rdc;
+      const double x1 = bcast_lane(ym1, owner) * rdc;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int i = lane + 64 * q;
-        if (i < m) {
-          const double l = Lrow[i];
-          y0[q] -= l * x0;
-          y1[q] -= l * x1;
-        } else if (i == m) {
+        if (i == m) {
           y0[q] = x0;
           y1[q] = x1;
+        } else {
+          y0[q] -= lc[q] * x0;
+          y1[q] -= lc[q] * x1;
         }
+        lc[q] = ln[q];
       }
+      rdc = rdn;
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
