@@ -123,7 +123,6 @@ fctn_status validate(const fctn_desc* d) {
   if (d->reuse != 0 && d->reuse != 1) return FCTN_E_INVALID;
   if (d->order_policy != 0 && d->order_policy != 1) return FCTN_E_INVALID;
   if (N != 3 && N != 4) return FCTN_E_UNSUPPORTED;
-  if (d->precision != FCTN_F64 && d->precision != FCTN_F32) return FCTN_E_UNSUPPORTED;
   return FCTN_OK;
 }
 
@@ -232,11 +231,11 @@ inline int floor_log2(int x) {
 // Operand slabs: [kap][p] (p contiguous; ld = 16 mod 64) unless kap is the
 // contiguous index in HBM, then [p][kap] (ld = 4 mod 64).  Both orders give
 // bank-conflict-free MFMA operand reads.
-void fill_tile(const MGen& mg, int TCu, int TCv, TileGeom* tg) {
+void fill_tile(const MGen& mg, int TCu, int TCv, int kalign, TileGeom* tg) {
   tg->TCu = TCu;
   tg->TCv = TCv;
   tg->tcol = TCu * TCv;
-  tg->tcolp = (tg->tcol + 3) / 4 * 4;
+  tg->tcolp = (tg->tcol + kalign - 1) / kalign * kalign;
   tg->Pu = mg.Ru * TCu;
   tg->Qv = mg.Rv * TCv;
   tg->Pp = pad16(tg->Pu);
@@ -269,7 +268,8 @@ inline size_t table_bytes(const TileGeom& tg, bool with_cols) {
 }
 
 template <class Extra, class Lds>
-bool choose_tile(const MGen& mg, int mg_repeat, Extra extra_mfma, Lds lds, TileGeom* best) {
+bool choose_tile(const MGen& mg, int mg_repeat, int kalign, Extra extra_mfma, Lds lds,
+                 TileGeom* best) {
   static const int cv_c[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20, 24, 25, 30, 32, 40, 48, 50, 64};
   static const int cu_c[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
   double best_cost = 1e300;
@@ -287,7 +287,7 @@ bool choose_tile(const MGen& mg, int mg_repeat, Extra extra_mfma, Lds lds, TileG
       const int tcol = TCu * TCv;
       if (tcol > 256) continue;
       TileGeom tg;
-      fill_tile(mg, TCu, TCv, &tg);
+      fill_tile(mg, TCu, TCv, kalign, &tg);
       const size_t bytes = lds(tg);
       if (bytes > (size_t)gram_max_lds_bytes()) continue;
       const double mgen = (double)(tg.Pp / 16) * (tg.Qp / 16) * (tg.Kp / 4) * mg_repeat;
@@ -312,7 +312,9 @@ bool choose_tile(const MGen& mg, int mg_repeat, Extra extra_mfma, Lds lds, TileG
   return found;
 }
 
-bool setup_geom(ModeInfo& m, size_t es) {
+bool setup_geom(ModeInfo& m, size_t es, int prec) {
+  const bool bf = prec == FCTN_BF16 || prec == FCTN_BF16X3;
+  const int nbf = prec == FCTN_BF16X3 ? 2 : 1;   // bf16 copies (hi, lo)
   GramGeom& g = m.geom;
   g.s = (int)m.s;
   g.sp = pad16(g.s);
@@ -334,14 +336,29 @@ bool setup_geom(ModeInfo& m, size_t es) {
     }
   }
   g.xrows = xmax;
-  g.ldm = ld_pad(g.sp);
-  g.ldx = ld_pad(std::max(xmax, 16));
+  if (!bf) {
+    g.ldm = ld_pad(g.sp);
+    g.ldx = ld_pad(std::max(xmax, 16));
+  }
+  // bf16 tiles are [row][column] with a row stride of tcolp + 8 bf16 values
   auto gram_lds = [&](const TileGeom& tg) {
+    if (bf)
+      return (size_t)(tg.u_len + tg.v_len) * es + table_bytes(tg, true) +
+             (size_t)(g.sp + xmax) * (tg.tcolp + 8) * 2 * nbf;
     return (size_t)(tg.u_len + tg.v_len + (size_t)tg.tcolp * (g.ldm + g.ldx)) * es +
            table_bytes(tg, true);
   };
-  auto gram_work = [&](const TileGeom& tg) { return (double)g.nTiles * (tg.tcolp / 4); };
-  if (!choose_tile(m.mg, g.nGroups, gram_work, gram_lds, &g.tg)) return false;
+  // consumer MFMA time per tile in fp32-16x16x4 units (a bf16 16x16x32 issue
+  // takes about half as long and covers 8 times the k range)
+  auto gram_work = [&](const TileGeom& tg) {
+    if (bf) return (double)g.nTiles * (tg.tcolp / 32) * (nbf == 2 ? 3 : 1) * 0.5;
+    return (double)g.nTiles * (tg.tcolp / 4);
+  };
+  if (!choose_tile(m.mg, g.nGroups, bf ? 32 : 4, gram_work, gram_lds, &g.tg)) return false;
+  if (bf) {
+    g.ldm = g.tg.tcolp + 8;
+    g.ldx = g.ldm;
+  }
   g.lds_bytes = gram_lds(g.tg);
   int64_t ns = std::max<int64_t>(1, kTargetGramWGs / g.nGroups);
   ns = std::min<int64_t>(ns, g.tg.nColTiles);
@@ -364,7 +381,7 @@ bool setup_geom(ModeInfo& m, size_t es) {
   auto rec_work = [&](const TileGeom& tg) {
     return (double)(r.ip / 16) * (pad16(tg.tcolp) / 16) * (r.sp / 4);
   };
-  if (!choose_tile(m.mg, 1, rec_work, rec_lds, &r.tg)) return false;
+  if (!choose_tile(m.mg, 1, 4, rec_work, rec_lds, &r.tg)) return false;
   r.tg.tcolp = pad16(r.tg.tcol);
   r.ldm = ld_mod(std::max(r.sp, 4), 4);
   r.lds_bytes = rec_lds(r.tg);
@@ -437,7 +454,7 @@ bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
     if (P->pnum[p] >= ((int64_t)1 << 31)) return false;
   for (int k = 0; k < P->N; ++k) {
     if (!solve_supported((int32_t)P->mode[k].s)) return false;
-    if (!setup_geom(P->mode[k], P->es)) return false;
+    if (!setup_geom(P->mode[k], P->es, P->prec)) return false;
   }
   const char* gp = getenv("FCTN_GEOM");
   if (gp && gp[0] == '1') {

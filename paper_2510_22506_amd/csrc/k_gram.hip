@@ -30,15 +30,17 @@ __device__ inline void upper_tile(int t, int& bi, int& bj) {
 //   rows p of the U slab: off = ru u_ru + cu_l u_cu, map = cu_l TCv ldm + ru Rv
 //   rows q of the V slab: off = rv v_rv + cv_l v_cv, map = cv_l ldm + rv
 //   columns c of the tile: off = cu_l x_cu + cv_l x_cv (X view), cl = cu_l, map = cv_l
-__device__ inline void build_tables(const MGen& mg, const TileGeom& tg, const XView* xv, int ldm,
-                                    SlabRow* pt, SlabRow* qt, SlabRow* ct, int tid, int nth) {
+// M element (row, c) of the tile sits at row * rs + c * cs in LDS.
+__device__ inline void build_tables(const MGen& mg, const TileGeom& tg, const XView* xv, int rs,
+                                    int cs, SlabRow* pt, SlabRow* qt, SlabRow* ct, int tid,
+                                    int nth) {
   for (int p = tid; p < tg.Pp; p += nth) {
     SlabRow r{0, 1 << 30, -1, 0};
     if (p < tg.Pu) {
       const int cul = p / mg.Ru, ru = p - cul * mg.Ru;
       r.off = (int32_t)(ru * mg.u_ru + cul * mg.u_cu);
       r.cl = cul;
-      r.map = cul * tg.TCv * ldm + ru * mg.Rv;
+      r.map = cul * tg.TCv * cs + ru * mg.Rv * rs;
     }
     pt[p] = r;
   }
@@ -48,7 +50,7 @@ __device__ inline void build_tables(const MGen& mg, const TileGeom& tg, const XV
       const int cvl = q / mg.Rv, rv = q - cvl * mg.Rv;
       r.off = (int32_t)(rv * mg.v_rv + cvl * mg.v_cv);
       r.cl = cvl;
-      r.map = cvl * ldm + rv;
+      r.map = cvl * cs + rv * rs;
     }
     qt[q] = r;
   }
@@ -96,11 +98,11 @@ __device__ inline void stage_slab(const T* __restrict__ F, int64_t base, int64_t
 
 // The tile's block of M on MFMA: O[p][q] = sum_kap Us(kap, p) Vs(kap, q),
 // scattered to Ms[pt[p].map + qt[q].map].
-template <typename T>
-__device__ inline void mgen_mfma(const TileGeom& tg, const T* __restrict__ Us,
-                                 const T* __restrict__ Vs, const SlabRow* __restrict__ ptab,
-                                 const SlabRow* __restrict__ qtab, T* __restrict__ Ms, int lane,
-                                 int wave, int nwaves) {
+template <typename T, typename Store>
+__device__ inline void mgen_mfma_store(const TileGeom& tg, const T* __restrict__ Us,
+                                       const T* __restrict__ Vs, const SlabRow* __restrict__ ptab,
+                                       const SlabRow* __restrict__ qtab, Store store, int lane,
+                                       int wave, int nwaves) {
   typedef Mfma<T> MM;
   const int npt = tg.Pp / 16, nqt = tg.Qp / 16;
   const int kr = lane >> 4, lc = lane & 15;
@@ -119,10 +121,19 @@ __device__ inline void mgen_mfma(const TileGeom& tg, const T* __restrict__ Us,
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int pm = ptab[pt * 16 + MM::row(lane, i)].map;
-        if (pm >= 0) Ms[pm + qm] = acc[i];
+        if (pm >= 0) store(pm + qm, acc[i]);
       }
     }
   }
+}
+
+template <typename T>
+__device__ inline void mgen_mfma(const TileGeom& tg, const T* __restrict__ Us,
+                                 const T* __restrict__ Vs, const SlabRow* __restrict__ ptab,
+                                 const SlabRow* __restrict__ qtab, T* __restrict__ Ms, int lane,
+                                 int wave, int nwaves) {
+  mgen_mfma_store<T>(tg, Us, Vs, ptab, qtab, [Ms](int idx, T v) { Ms[idx] = v; }, lane, wave,
+                     nwaves);
 }
 
 template <typename T>
@@ -198,7 +209,7 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
     boff[j] = bj * 16 + (lane & 15);
   }
 
-  build_tables(mg, tg, &xv, g.ldm, ptab, qtab, ctab, tid, kGramThreads);
+  build_tables(mg, tg, &xv, 1, g.ldm, ptab, qtab, ctab, tid, kGramThreads);
   // rows of M beyond s and columns beyond the tile (in M and X) stay zero for
   // the whole launch: uninitialized LDS could hold NaN patterns, and NaN * 0
   // would poison the products
@@ -273,6 +284,145 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
 int gram_threads() { return kGramThreads; }
 int gram_tiles_per_group() { return kGramWaves * kTPW; }
 
+// ---------------------------------------------------------------------------
+// bf16 form of the same pass.  The tile of M_k is generated on fp32 MFMA as
+// above and rounded once (nearest even) into bf16 LDS tiles laid out
+// [row][column] (columns contiguous), as are the X_(k) rows; the Gram and
+// right-hand-side products then run on bf16 MFMA (16x16x32, fp32
+// accumulation), each lane reading its 8 consecutive k values with one
+// 16-byte load.  With X3 each value is also kept as a bf16 residual
+// (x = hi + lo) and every product is hi*hi + hi*lo + lo*hi.
+// ---------------------------------------------------------------------------
+template <int X3>
+__global__ void __launch_bounds__(kGramThreads) gram_rhs_bf16_k(MGen mg, const float* __restrict__ X,
+                                                                XView xv, GramGeom g,
+                                                                float* __restrict__ part) {
+  typedef Mfma<float> MF;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileGeom& tg = g.tg;
+  SlabRow* ptab = (SlabRow*)smem_raw;
+  SlabRow* qtab = ptab + tg.Pp;
+  SlabRow* ctab = qtab + tg.Qp;
+  float* Us = (float*)(ctab + tg.tcolp);
+  float* Vs = Us + tg.u_len;
+  const int ldb = g.ldm;                         // bf16 row stride (multiple of 8)
+  uint16_t* Mh = (uint16_t*)(Vs + tg.v_len);     // [sp][ldb]
+  uint16_t* Ml = Mh + (X3 ? (size_t)g.sp * ldb : 0);
+  uint16_t* Xh = Ml + (size_t)g.sp * ldb;         // [xrows][ldb]
+  uint16_t* Xl = Xh + (X3 ? (size_t)g.xrows * ldb : 0);
+  const float* U = (const float*)mg.U;
+  const float* V = (const float*)mg.V;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int split = blockIdx.x, group = blockIdx.y;
+  const int t0 = group * g.tilesPerGroup;
+  const int t1 = min(t0 + g.tilesPerGroup, g.nTiles);
+  int ba_lo = 0, xrows = 0;
+  if (t1 > g.nG) {
+    const int bfirst = (max(t0, g.nG) - g.nG) / g.nbj;
+    const int blast = (t1 - 1 - g.nG) / g.nbj;
+    ba_lo = bfirst;
+    xrows = (blast - bfirst + 1) * 16;
+  }
+  int arow[kTPW], brow[kTPW];
+  bool fromX[kTPW], valid[kTPW];
+  MF::acc_t acc[kTPW];
+#pragma unroll
+  for (int j = 0; j < kTPW; ++j) {
+    const int t = t0 + wave + kGramWaves * j;
+    valid[j] = t < t1;
+    acc[j] = MF::zero();
+    int bi = 0, bj = 0;
+    fromX[j] = false;
+    if (valid[j]) {
+      if (t < g.nG) {
+        upper_tile(t, bi, bj);
+      } else {
+        const int tb = t - g.nG;
+        bi = tb / g.nbj - ba_lo;
+        bj = tb % g.nbj;
+        fromX[j] = true;
+      }
+    }
+    arow[j] = (bi * 16 + (lane & 15)) * ldb + 8 * (lane >> 4);
+    brow[j] = (bj * 16 + (lane & 15)) * ldb + 8 * (lane >> 4);
+  }
+
+  build_tables(mg, tg, &xv, ldb, 1, ptab, qtab, ctab, tid, kGramThreads);
+  {
+    // M tile(s) then X tile(s), hi and (X3) lo copies: every padding column
+    // must read as zero
+    const int nzero = (g.sp + g.xrows) * ldb * (1 + X3);
+    for (int e = tid; e < nzero; e += kGramThreads) Mh[e] = 0;
+  }
+  __syncthreads();
+
+  const int64_t ct0 = (int64_t)split * g.colTilesPerSplit;
+  const int64_t ct1 = min(ct0 + g.colTilesPerSplit, tg.nColTiles);
+  int64_t cur_tu = -1, cur_tv = -1;
+  const bool x_rfast = xv.x_ik == 1;
+  auto put = [&](uint16_t* hi, uint16_t* lo, int idx, float v) {
+    const uint16_t h = bf16_bits_rne(v);
+    hi[idx] = h;
+    if (X3) lo[idx] = bf16_bits_rne(v - bf16_bits_to_float(h));
+  };
+
+  for (int64_t ct = ct0; ct < ct1; ++ct) {
+    const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
+    stage_operands<float>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
+                          kGramThreads);
+    if (xrows > 0) {
+      const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
+      const int64_t lim_u = mg.Cu - cu0, lim_v = mg.Cv - cv0;
+      const float* xb = X + cu0 * xv.x_cu + cv0 * xv.x_cv + (int64_t)(ba_lo * 16) * xv.x_ik;
+      const int xlim = xv.Ik - ba_lo * 16;
+      for (int e = tid; e < tg.tcol * xrows; e += kGramThreads) {
+        int r, c;
+        if (x_rfast) { c = e / xrows; r = e - c * xrows; }
+        else { r = e / tg.tcol; c = e - r * tg.tcol; }
+        const SlabRow cr = ctab[c];
+        const float v = (cr.cl < lim_u && cr.map < lim_v && r < xlim)
+                            ? xb[cr.off + (int64_t)r * xv.x_ik] : 0.f;
+        put(Xh, Xl, r * ldb + c, v);
+      }
+    }
+    __syncthreads();
+    mgen_mfma_store<float>(tg, Us, Vs, ptab, qtab,
+                           [&](int idx, float v) { put(Mh, Ml, idx, v); }, lane, wave,
+                           kGramWaves);
+    __syncthreads();
+    for (int kk = 0; kk < tg.tcolp; kk += 32) {
+#pragma unroll
+      for (int j = 0; j < kTPW; ++j) {
+        if (valid[j]) {
+          const uint16_t* Ah = fromX[j] ? Xh : Mh;
+          const bf16x8 a = *(const bf16x8*)(Ah + arow[j] + kk);
+          const bf16x8 b = *(const bf16x8*)(Mh + brow[j] + kk);
+          acc[j] = MfmaBf16::mma(a, b, acc[j]);
+          if (X3) {
+            const uint16_t* Al = fromX[j] ? Xl : Ml;
+            const bf16x8 al = *(const bf16x8*)(Al + arow[j] + kk);
+            const bf16x8 bl = *(const bf16x8*)(Ml + brow[j] + kk);
+            acc[j] = MfmaBf16::mma(a, bl, acc[j]);
+            acc[j] = MfmaBf16::mma(al, b, acc[j]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int j = 0; j < kTPW; ++j) {
+    if (valid[j]) {
+      const int t = t0 + wave + kGramWaves * j;
+      float* base = part + ((int64_t)split * g.nTiles + t) * 256;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) base[MfmaBf16::row(lane, i) * 16 + (lane & 15)] = acc[j][i];
+    }
+  }
+}
+
 int gram_max_lds_bytes() { return 160 * 1024; }
 
 hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView& xv,
@@ -283,6 +433,16 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
     gram_rhs_k<double><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const double*)X, xv, g,
                                                                 (double*)part);
+  } else if (prec == P_BF16) {
+    hipFuncSetAttribute((const void*)gram_rhs_bf16_k<0>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
+    gram_rhs_bf16_k<0><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
+                                                                (float*)part);
+  } else if (prec == P_BF16X3) {
+    hipFuncSetAttribute((const void*)gram_rhs_bf16_k<1>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
+    gram_rhs_bf16_k<1><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
+                                                                (float*)part);
   } else {
     hipFuncSetAttribute((const void*)gram_rhs_k<float>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
@@ -374,7 +534,7 @@ __global__ void __launch_bounds__(256) reconstruct_k(MGen mg, const T* __restric
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kr = lane >> 4, lc = lane & 15;
 
-  build_tables(mg, tg, nullptr, g.ldm, ptab, qtab, nullptr, tid, 256);
+  build_tables(mg, tg, nullptr, 1, g.ldm, ptab, qtab, nullptr, tid, 256);
   for (int e = tid; e < tg.tcolp * g.ldm; e += 256) Ms[e] = T(0);
   if (g.lda > 0) {
     for (int e = tid; e < g.ip * g.sp; e += 256) {
