@@ -194,7 +194,8 @@ enum {
   FCTN_STAGE_GRAM_RHS = 1,    /* fused M_k generation + Gram + RHS (eq. 5)   */
   FCTN_STAGE_REDUCE = 2,      /* float64 split-K reduction (+ rho A_k)        */
   FCTN_STAGE_SOLVE = 3,       /* per-class Cholesky solves (eq. 5-8)          */
-  FCTN_STAGE_BACKTRANSFORM = 4, /* A = Q A~, fold (eq. 9), casts             */
+  FCTN_STAGE_TRANSFORM = 4,   /* basis changes Q^T B and Q A~ (eq. 8), fold
+                                 (eq. 9), casts                              */
   FCTN_STAGE_RECONSTRUCT = 5, /* Z = A_last M'_last (Algorithm 2, X step)    */
   FCTN_STAGE_XUPDATE = 6,     /* eq. 10 select + norm partials               */
   FCTN_STAGE_STATS = 7,       /* per-sweep scalars                           */

@@ -571,14 +571,17 @@ fctn_status gram_rhs(fctn_plan_s* P, int k, double* G, double* B) {
 fctn_status solve(fctn_plan_s* P, int k, const double* G, const double* B) {
   const ModeInfo& m = P->mode[k];
   const double s3 = (double)m.s * m.s * m.s;
-  FCTN_TIMED(P, FCTN_STAGE_SOLVE,
-             m.ncls * (s3 / 3.0 + 4.0 * m.s * m.s) + 4.0 * m.Ik * m.Ik * m.s,
-             8.0 * (m.s * m.s + 2.0 * m.Ik * m.s + m.Ik * m.Ik),
-             launch_solve_classes(G, B, P->Qt[k], (int32_t)m.Ik, (int32_t)m.s, P->d.lambda[k],
+  const double tr_flops = 2.0 * m.Ik * m.Ik * m.s;
+  const double tr_bytes = 8.0 * (m.Ik * m.Ik + 2.0 * m.Ik * m.s);
+  // b~ = Q^T B into At; the solves overwrite each class's rows with a~
+  FCTN_TIMED(P, FCTN_STAGE_TRANSFORM, tr_flops, tr_bytes,
+             launch_project(P->Qt[k], B, (int32_t)m.Ik, (int32_t)m.s, P->At, P->st));
+  FCTN_TIMED(P, FCTN_STAGE_SOLVE, m.ncls * (s3 / 3.0 + 4.0 * m.s * m.s),
+             8.0 * (m.s * m.s + 2.0 * m.Ik * m.s),
+             launch_solve_classes(G, (int32_t)m.Ik, (int32_t)m.s, P->d.lambda[k],
                                   P->d.delta[k], P->d.rho, P->At,
                                   P->trace_part + (size_t)k * P->max_cls, P->st));
-  FCTN_TIMED(P, FCTN_STAGE_BACKTRANSFORM, 2.0 * m.Ik * m.Ik * m.s,
-             8.0 * (m.Ik * m.Ik + 2.0 * m.Ik * m.s) + 2.0 * m.Ik * m.s * P->es,
+  FCTN_TIMED(P, FCTN_STAGE_TRANSFORM, tr_flops, tr_bytes + 2.0 * m.Ik * m.s * P->es,
              launch_backtransform(P->prec, P->Q[k], P->At, (int32_t)m.Ik, (int32_t)m.s,
                                   m.spost, P->A64[k], P->Aw[k], P->Au[k], P->st));
   P->fver[k]++;

@@ -5,15 +5,18 @@
 // A~ = Q^T A turns eq. 5 into one equation per row of A~:
 //     a~_v (G + (lambda Lambda_v + rho) I) = b~_v,   b~ = Q^T B.
 // Rows that share a frequency share the matrix, so each frequency class is
-// one SPD solve.  solve_classes_k runs one class per workgroup: b~ by
-// wavefront-level reductions over i_k, then a register-resident Cholesky of
-// the shifted G (1024 threads, 32x32 cyclic distribution) with the class's
-// right-hand sides appended as extra rows (their rows of the factor are the
-// forward-substitution result), then back substitution.  The same unique
-// solution as eq. 8 (the shifted matrix is positive definite), reached
-// without an eigendecomposition of G.  backtransform_k forms A = Q A~ and
-// stores it folded (eq. 9) in float64 and in the working precision.
+// one SPD solve.  The two basis changes are float64 MFMA products
+// (gemm64_k): b~ = Q^T B for all rows at once before the solves, and
+// A = Q A~ after them, stored folded (eq. 9) in float64 and in the working
+// precision.  solve_classes_k runs one class per workgroup: a blocked
+// right-looking Cholesky of the shifted G with the class's right-hand sides
+// appended as extra rows (their rows of the factor are the forward-
+// substitution result), then a blocked back substitution, overwriting the
+// class's rows of b~ with those of a~.  The same unique solution as eq. 8
+// (the shifted matrix is positive definite), reached without an
+// eigendecomposition of G.
 #include <algorithm>
+#include <utility>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -22,21 +25,63 @@ namespace fctn {
 
 int solve_supported(int32_t s) { return s >= 1 && s <= 192; }
 
+// Phase hook for timing probes (empty in the library).
+#ifndef FCTN_SOLVE_MARK
+#define FCTN_SOLVE_MARK(n)
+#endif
+
+// Calls f(integral_constant<int, 0>) .. f(integral_constant<int, N - 1>) in
+// order, so that register arrays indexed by the constant stay in registers.
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// LDS of solve_classes_k, in doubles: two transposed panels (32 x 32 SB
+// each), the right-hand sides (2 x 32 SB), reciprocal pivots (32 SB), the
+// back-substitution partials (64), a wave-sum buffer (16) and the column
+// counter of the diagonal block (one word).
+static inline size_t solve_lds_doubles(int sb) { return (size_t)67 * 32 * sb + 81; }
+
+// Layout: thread (r, cc) = (tid % 32, tid / 32) holds H[r + 32a][cc + 32b]
+// for the lower blocks b <= a in registers (32x32 cyclic over 1024 threads).
+// Panel p (columns 32p .. 32p + 31) is staged transposed in LDS,
+// pan[jj][i] = H[i][32p + jj], so that a half-wave reads 32 consecutive rows.
+// Per panel, with a workgroup barrier after (a)+(b) and after (c):
+//   (a) wave 0 factors the 32x32 diagonal block column by column; lanes
+//       (i, h) hold row i, columns 16h .. 16h + 15; each finished column is
+//       broadcast through LDS within the wave (no workgroup barrier);
+//   (b) meanwhile other waves solve the rows below the block, and the two
+//       right-hand-side rows, against the block's factor (TRSM), following
+//       the published columns through an LDS counter;
+//   (c) every thread keeps its finished part of the column block, applies
+//       the rank-32 update to its trailing blocks, updates the right-hand
+//       sides and writes the next column block into the other panel buffer.
+// Back substitution runs over the panels in reverse: a half-wave reduction
+// of the already-solved rows, then a 32-step solve against the diagonal
+// block in one wave (register values broadcast by readlane).
 template <int SB>
-__global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict__ G,
-                                                        const double* __restrict__ B,
-                                                        const double* __restrict__ Qt, int Ik,
+__global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict__ G, int Ik,
                                                         int s, double lam, double delta,
                                                         double rho, double* __restrict__ At,
                                                         double* __restrict__ trace_part) {
-  __shared__ double colbuf[2][2][32 * SB];
-  __shared__ double rhs[2][32 * SB];
-  __shared__ double diag[32 * SB];
-  __shared__ double rdiag[32 * SB];
-  __shared__ double red[16];
-  extern __shared__ double Lp[];   // s (s + 1) / 2 packed lower factor
+  constexpr int LDP = 32 * SB;
+  extern __shared__ double smem[];
+  double* const pan0 = smem;
+  double* const pan1 = smem + 32 * LDP;
+  double* const rhs = smem + 64 * LDP;
+  double* const rdiag = rhs + 2 * LDP;
+  double* const tpart = rdiag + LDP;
+  double* const red = tpart + 64;
+  int* const pub = (int*)(red + 16);
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = tid & 31, cc = tid >> 5;
+  FCTN_SOLVE_MARK(0);
 
   int nv = 2, v0 = 2 * c - 1, v1 = 2 * c;
   if (c == 0) {
@@ -48,33 +93,21 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
   const double Lam = delta + 4.0 * sn * sn;
   const double sigma = lam * Lam + rho;
 
-  // b~_v[m] = sum_i Q[i][v] B[i][m]: output o = (v, m) gets nsub threads that
-  // each sum an interleaved slice of i (reads coalesced over m); the slices
-  // are combined in a fixed order through LDS (the L buffer, unused yet)
-  {
-    const int nout = 2 * s;
-    const int nsub = 1024 / nout;
-    const int o = tid % nout, sub = tid / nout;
-    if (sub < nsub) {
-      const int v = o >= s ? 1 : 0, m = o - v * s;
-      const double* q = Qt + (int64_t)(v ? v1 : v0) * Ik;
-      double p = 0.0;
-      for (int i = sub; i < Ik; i += nsub) p += q[i] * B[(int64_t)i * s + m];
-      Lp[sub * nout + o] = p;
-    }
-    __syncthreads();
-    if (tid < nout) {
-      double p = 0.0;
-      for (int k = 0; k < nsub; ++k) p += Lp[k * nout + tid];
-      rhs[tid >= s ? 1 : 0][tid >= s ? tid - s : tid] = p;
-    }
-  }
+  // every LDS word starts finite: padding rows and columns are read (and
+  // multiplied by zero or discarded) but never decide a result
+  for (int t = tid; t < 67 * LDP; t += 1024) smem[t] = 0.0;
+  __syncthreads();
+  FCTN_SOLVE_MARK(1);
 
-  // H = G + sigma I, 32x32 cyclic: thread (r, c) = (tid % 32, tid / 32) holds
-  // rows r + 32a and columns c + 32b (lower blocks b <= a only).  The 32
-  // holders of a column are one half-wave.  G is symmetric, so G[m][i] is read
-  // (consecutive lanes, consecutive addresses).
-  const int r = tid & 31, cc = tid >> 5;
+  // the class's rows of b~
+  for (int t = tid; t < 2 * s; t += 1024) {
+    const int v = t >= s ? 1 : 0, m = t - v * s;
+    rhs[v * LDP + m] = At[(int64_t)(v ? v1 : v0) * s + m];
+  }
+  FCTN_SOLVE_MARK(2);
+
+  // H = G + sigma I (G symmetric: G[m][i] is read, consecutive over r), and
+  // column block 0 staged
   double H[SB][SB];
 #pragma unroll
   for (int a = 0; a < SB; ++a) {
@@ -85,236 +118,195 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
       H[a][b] = (i < s && m <= i) ? G[(int64_t)m * s + i] + (i == m ? sigma : 0.0) : 0.0;
     }
   }
-  __syncthreads();
-
-  // Right-looking Cholesky, two columns per barrier.  Columns j (even) and
-  // j + 1 are held by the two halves of one wave (lanes 0-31: column j, rows
-  // r + 32a; lanes 32-63: column j + 1).  That wave factors both without a
-  // workgroup barrier: pivot j by readlane, column j scaled and published to
-  // LDS, column j + 1 updated from it (same wave, in-order LDS), pivot j + 1,
-  // column j + 1 published.  After the barrier every thread applies the
-  // rank-2 update to its trailing blocks.  Multipliers outside the trailing
-  // range are zero, so the update needs no per-element tests (strictly upper
-  // entries of diagonal blocks receive values that are never read).
-  for (int j = 0; j < s; j += 2) {
-    const int jb = j >> 5, jt = j & 31;
-    const bool two = j + 1 < s;
-    const int jlast = two ? j + 1 : j;
-    double* cb0 = colbuf[(j >> 1) & 1][0];
-    double* cb1 = colbuf[(j >> 1) & 1][1];
-    if (wave == (jt >> 1)) {
-      const int half = lane >> 5;
-      // this lane's column (j or j + 1), raw
-      double v[SB];
-#pragma unroll
-      for (int a = 0; a < SB; ++a) {
-        v[a] = 0.0;
-#pragma unroll
-        for (int b = 0; b <= a; ++b)
-          if (b == jb) v[a] = H[a][b];
-      }
-      double vj = 0.0;
-#pragma unroll
-      for (int a = 0; a < SB; ++a)
-        if (a == jb) vj = v[a];
-      const double d0 = bcast_lane(vj, jt);
-      const double rs0 = rsqrt_f64(d0);
-      const double sd0 = d0 * rs0;
-#pragma unroll
-      for (int a = 0; a < SB; ++a) {
-        const int i = r + 32 * a;
-        if (half == 0 && i > j && i < s) cb0[i] = v[a] * rs0;
-      }
-      double rs1 = 0.0, sd1 = 0.0;
-      if (two) {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const double l10 = cb0[j + 1];
-#pragma unroll
-        for (int a = 0; a < SB; ++a) {
-          const int i = r + 32 * a;
-          if (half == 1 && i > j && i < s) v[a] -= cb0[i] * l10;
-        }
-        double vj1 = 0.0;
-#pragma unroll
-        for (int a = 0; a < SB; ++a)
-          if (a == jb) vj1 = v[a];
-        const double d1 = bcast_lane(vj1, 32 + jt + 1);
-        rs1 = rsqrt_f64(d1);
-        sd1 = d1 * rs1;
-#pragma unroll
-        for (int a = 0; a < SB; ++a) {
-          const int i = r + 32 * a;
-          if (half == 1 && i > j + 1 && i < s) cb1[i] = v[a] * rs1;
-        }
-      }
-      // the owning lanes keep their finished column of L
-      const int jc = j + half;
-      const double rsc = half ? rs1 : rs0, sdc = half ? sd1 : sd0;
-#pragma unroll
-      for (int a = 0; a < SB; ++a) {
-        const int i = r + 32 * a;
-#pragma unroll
-        for (int b = 0; b <= a; ++b)
-          if (b == jb && jc < s) H[a][b] = (i == jc) ? sdc : ((i > jc && i < s) ? v[a] * rsc : H[a][b]);
-      }
-      if (lane == 0) {
-        diag[j] = sd0;
-        rdiag[j] = rs0;
-        if (two) {
-          diag[j + 1] = sd1;
-          rdiag[j + 1] = rs1;
-        }
-      }
-    }
-    __syncthreads();
-    double lm0[SB], lm1[SB], li0[SB], li1[SB];
-#pragma unroll
-    for (int b = 0; b < SB; ++b) {
-      const int m = cc + 32 * b, i = r + 32 * b;
-      const bool act = 32 * b + 31 > jlast;
-      const bool okm = act && m > jlast && m < s, oki = act && i > jlast && i < s;
-      lm0[b] = okm ? cb0[m] : 0.0;
-      li0[b] = oki ? cb0[i] : 0.0;
-      lm1[b] = (two && okm) ? cb1[m] : 0.0;
-      li1[b] = (two && oki) ? cb1[i] : 0.0;
-    }
-#pragma unroll
-    for (int a = 0; a < SB; ++a) {
-      if (32 * a + 31 <= jlast) continue;
-#pragma unroll
-      for (int b = 0; b <= a; ++b) {
-        if (32 * b + 31 <= jlast) continue;
-        H[a][b] -= li0[a] * lm0[b] + li1[a] * lm1[b];
-      }
-    }
-  }
-  // L to LDS (packed lower: row i starts at i (i + 1) / 2)
 #pragma unroll
   for (int a = 0; a < SB; ++a) {
     const int i = r + 32 * a;
-#pragma unroll
-    for (int b = 0; b <= a; ++b) {
-      const int m = cc + 32 * b;
-      if (i < s && m <= i) Lp[i * (i + 1) / 2 + m] = H[a][b];
-    }
+    if (i < s) pan0[cc * LDP + i] = H[a][0];
   }
+  if (tid == 0) *pub = 0;
   __syncthreads();
+  FCTN_SOLVE_MARK(3);
 
-  // forward (L y = b~) and back (L^T x = y) substitution in one wave,
-  // column-oriented: lane l keeps entries i = l + 64 q in registers; the
-  // pivot entry is broadcast from its owner lane with readlane.  The next
-  // step's column (row) of L and its reciprocal pivot are loaded while the
-  // current step's updates run.
-  if (wave == 0) {
-    constexpr int NQ = (32 * SB + 63) / 64;
-    double y0[NQ], y1[NQ];
-    int rowbase[NQ];
+  static_for<SB>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = decltype(pc)::value;
+    const int p0 = 32 * p;
+    if (p0 < s) {
+    const int np = min(32, s - p0);
+    double* const pan = (p & 1) ? pan1 : pan0;
+    double* const pnx = (p & 1) ? pan0 : pan1;
+
+    // (a) diagonal block, wave 0.  Column j is published with zeros at and
+    // above the diagonal, so every later product with an entry that must not
+    // act (a finished column, a row at or above the pivot) multiplies a stored
+    // zero; the pivots live in rdiag only.  After each column the counter
+    // *pub is raised (release), so that (b) can follow column by column.
+    // (b) rows below the block and the right-hand sides (TRSM), waves 1-3
+    // and 5-15 (SIMD 0 is left to wave 0).  Each row is split over the two
+    // halves of a wave (lanes l and l + 32 hold columns 0-15 and 16-31 of the
+    // same row); a finished value of the first half reaches the second half
+    // by one cross-half shuffle.  Step j waits (acquire) for column j.
+    const int nbelow = max(s - p0 - 32, 0);
+    if (wave == 0) {
+      const int i = lane & 31, h = lane >> 5;
+      double d[16];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = lane + 64 * q;
-      y0[q] = i < s ? rhs[0][i] : 0.0;
-      y1[q] = i < s ? rhs[1][i] : 0.0;
-      rowbase[q] = i * (i + 1) / 2;
-    }
-    // forward: column m of L is Lp[rowbase(i) + m] for i > m
-    double lc[NQ], ln[NQ];
+      for (int q = 0; q < 16; ++q) d[q] = pan[(16 * h + q) * LDP + p0 + i];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = lane + 64 * q;
-      lc[q] = (i > 0 && i < s) ? Lp[rowbase[q]] : 0.0;
-    }
-    double rdc = rdiag[0];
-    for (int m = 0; m < s; ++m) {
-      const int mn = m + 1;
+      for (int j = 0; j < 32; ++j) {
+        if (j < np) {
+          const int hj = j >> 4, cj = j & 15;
+          const double piv = bcast_lane(d[cj], j + 32 * hj);
+          const double rs = rsqrt_f64(piv);
+          const double lv = i > j ? d[cj] * rs : 0.0;
+          if (h == hj) pan[j * LDP + p0 + i] = lv;
+          if (lane == 0) {
+            rdiag[p0 + j] = rs;
+            __hip_atomic_store(pub, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          const double lij = pan[j * LDP + p0 + i];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int i = lane + 64 * q;
-        ln[q] = (mn < s && i > mn && i < s) ? Lp[rowbase[q] + mn] : 0.0;
-      }
-      const double rdn = mn < s ? rdiag[mn] : 0.0;
-      const int owner = m & 63, qm = m >> 6;
-      double ym0 = 0.0, ym1 = 0.0;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (q == qm) {
-          ym0 = y0[q];
-          ym1 = y1[q];
+          for (int q = 0; q < 16; ++q) d[q] -= lij * pan[j * LDP + p0 + 16 * h + q];
         }
-      const double x0 = bcast_lane(ym0, owner) * rdc;
-      const double x1 = bcast_lane(ym1, owner) * rdc;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int i = lane + 64 * q;
-        if (i == m) {
-          y0[q] = x0;
-          y1[q] = x1;
-        } else {
-          y0[q] -= lc[q] * x0;
-          y1[q] -= lc[q] * x1;
-        }
-        lc[q] = ln[q];
       }
-      rdc = rdn;
-    }
-    // back: row m of L is Lp[m (m + 1) / 2 + i] for i < m
-    const int ms = s - 1;
+    } else if (wave != 4 && (wave - 1 - (wave > 4)) * 32 < nbelow + 2) {
+      const int row = (wave - 1 - (wave > 4)) * 32 + (lane & 31), h = lane >> 5;
+      const bool valid = row < nbelow + 2;
+      const int v = valid ? row - nbelow : 0;
+      double* const base = v < 0 ? pan + p0 + 32 + row : rhs + v * LDP + p0;
+      const int stride = v < 0 ? LDP : 1;
+      double x[16];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = lane + 64 * q;
-      lc[q] = (i < ms) ? Lp[ms * (ms + 1) / 2 + i] : 0.0;
-    }
-    rdc = rdiag[ms];
-    for (int m = ms; m >= 0; --m) {
-      const int mn = m - 1;
+      for (int q = 0; q < 16; ++q) x[q] = base[(16 * h + q) * stride];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int i = lane + 64 * q;
-        ln[q] = (mn >= 0 && i < mn) ? Lp[mn * (mn + 1) / 2 + i] : 0.0;
-      }
-      const double rdn = mn >= 0 ? rdiag[mn] : 0.0;
-      const int owner = m & 63, qm = m >> 6;
-      double ym0 = 0.0, ym1 = 0.0;
+      for (int j = 0; j < 32; ++j) {
+        if (j < np) {
+          // bounded wait: column j is always published (j < np), the bound
+          // only guards against a logic error turning into a hang
+          for (int spin = 0; spin < (1 << 16); ++spin) {
+            if (__hip_atomic_load(pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) > j) break;
+            __builtin_amdgcn_s_sleep(1);
+          }
+          const int hj = j >> 4, cj = j & 15;
+          const double sc = h == hj ? rdiag[p0 + j] : 1.0;
+          x[cj] *= sc;
+          double xj = x[cj];
+          if (hj == 0) {
+            const double o = __shfl_xor(xj, 32, kWave);
+            xj = h ? o : xj;
+          }
+          // entries at and above the diagonal of column j are stored zeros
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (q == qm) {
-          ym0 = y0[q];
-          ym1 = y1[q];
+          for (int q = 0; q < 16; ++q) x[q] -= xj * pan[j * LDP + p0 + 16 * h + q];
         }
-      const double x0 = bcast_lane(ym0, owner) * rdc;
-      const double x1 = bcast_lane(ym1, owner) * rdc;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int i = lane + 64 * q;
-        if (i == m) {
-          y0[q] = x0;
-          y1[q] = x1;
-        } else {
-          y0[q] -= lc[q] * x0;
-          y1[q] -= lc[q] * x1;
-        }
-        lc[q] = ln[q];
+        __builtin_amdgcn_sched_barrier(0);
       }
-      rdc = rdn;
-    }
+      if (valid) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = lane + 64 * q;
+        for (int q = 0; q < 16; ++q)
+          if (16 * h + q < np) base[(16 * h + q) * stride] = x[q];
+      }
+    }
+    __syncthreads();
+    FCTN_SOLVE_MARK(5 + 3 * p);
+
+    // (c) keep the finished column block, trailing update, next panel out
+    // strictly lower part of the diagonal block (the stored diagonal is zero)
+    H[p][p] = pan[cc * LDP + p0 + r];
+#pragma unroll
+    for (int a = p + 1; a < SB; ++a) H[a][p] = pan[cc * LDP + r + 32 * a];
+    if (nbelow > 0) {
+#pragma unroll 2
+      for (int jj = 0; jj < 32; ++jj) {
+        double li[SB], lm[SB];
+#pragma unroll
+        for (int a = p + 1; a < SB; ++a) {
+          li[a] = pan[jj * LDP + r + 32 * a];
+          lm[a] = pan[jj * LDP + cc + 32 * a];
+        }
+#pragma unroll
+        for (int a = p + 1; a < SB; ++a)
+#pragma unroll
+          for (int b = p + 1; b <= a; ++b) H[a][b] -= li[a] * lm[b];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      for (int t = tid; t < 2 * nbelow; t += 1024) {
+        const int v = t >= nbelow ? 1 : 0;
+        const int m = p0 + 32 + t - v * nbelow;
+        double acc = rhs[v * LDP + m];
+        for (int jj = 0; jj < 32; ++jj) acc -= rhs[v * LDP + p0 + jj] * pan[jj * LDP + m];
+        rhs[v * LDP + m] = acc;
+      }
+      if constexpr (p + 1 < SB) {
+#pragma unroll
+        for (int a = p + 1; a < SB; ++a) {
+          const int i = r + 32 * a;
+          if (i < s) pnx[cc * LDP + i] = H[a][p + 1];
+        }
+      }
+    }
+    if (tid == 0) *pub = 0;
+    __syncthreads();
+    FCTN_SOLVE_MARK(6 + 3 * p);
+    }
+  });
+
+  // back substitution L^T x = y, panels in reverse
+  static_for<SB>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = SB - 1 - decltype(pc)::value;
+    const int p0 = 32 * p;
+    if (p0 < s) {
+    const int np = min(32, s - p0);
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int a = p + 1; a < SB; ++a) {
+      const int i = r + 32 * a;
       if (i < s) {
-        rhs[0][i] = y0[q];
-        rhs[1][i] = y1[q];
+        t0 += H[a][p] * rhs[i];
+        t1 += H[a][p] * rhs[LDP + i];
       }
     }
-  }
-  __syncthreads();
+#pragma unroll
+    for (int off = 16; off >= 1; off >>= 1) {
+      t0 += __shfl_xor(t0, off, 32);
+      t1 += __shfl_xor(t1, off, 32);
+    }
+    if (r == 0) {
+      tpart[cc] = t0;
+      tpart[32 + cc] = t1;
+    }
+    smem[r * 33 + cc] = H[p][p];
+    __syncthreads();
+    FCTN_SOLVE_MARK(24 + 2 * p);
+    if (wave == 0) {
+      const int q = lane & 31, v = lane >> 5;
+      double z = q < np ? rhs[v * LDP + p0 + q] - tpart[v * 32 + q] : 0.0;
+#pragma unroll
+      for (int j = 31; j >= 0; --j) {
+        if (j < np) {
+          const double za = bcast_lane(z, j), zb = bcast_lane(z, 32 + j);
+          const double xj = (v ? zb : za) * rdiag[p0 + j];
+          const double raw = smem[j * 33 + q];
+          const double l = q < j ? raw : 0.0;
+          z = q == j ? xj : z - l * xj;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (q < np) rhs[v * LDP + p0 + q] = z;
+    }
+    __syncthreads();
+    FCTN_SOLVE_MARK(25 + 2 * p);
+    }
+  });
 
   double tr = 0.0;
   for (int m = tid; m < s; m += 1024) {
-    const double x0 = rhs[0][m];
+    const double x0 = rhs[m];
     At[(int64_t)v0 * s + m] = x0;
     tr += x0 * x0;
     if (nv == 2) {
-      const double x1 = rhs[1][m];
+      const double x1 = rhs[LDP + m];
       At[(int64_t)v1 * s + m] = x1;
       tr += x1 * x1;
     }
@@ -327,21 +319,21 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
     for (int w = 0; w < 16; ++w) t += red[w];
     trace_part[c] = Lam * t;
   }
+  FCTN_SOLVE_MARK(40);
 }
 
-hipError_t launch_solve_classes(const double* G, const double* B, const double* Qt,
-                                int32_t Ik, int32_t s, double lam, double delta, double rho,
-                                double* At, double* trace_part, hipStream_t st) {
+hipError_t launch_solve_classes(const double* G, int32_t Ik, int32_t s, double lam,
+                                double delta, double rho, double* At, double* trace_part,
+                                hipStream_t st) {
   const int ncls = Ik / 2 + 1;
   const int sb = (s + 31) / 32;
-  // packed factor, or the projection partials before it exists
-  const size_t lds = (size_t)std::max(s * (s + 1) / 2, 1024) * sizeof(double);
+  const size_t lds = solve_lds_doubles(sb) * sizeof(double);
   switch (sb) {
 #define FCTN_SOLVE_CASE(N)                                                                 \
   case N:                                                                                  \
     hipFuncSetAttribute((const void*)solve_classes_k<N>,                                   \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);             \
-    solve_classes_k<N><<<ncls, 1024, lds, st>>>(G, B, Qt, Ik, s, lam, delta, rho, At,    \
+    solve_classes_k<N><<<ncls, 1024, lds, st>>>(G, Ik, s, lam, delta, rho, At,           \
                                                 trace_part);                               \
     break;
     FCTN_SOLVE_CASE(1)
@@ -357,53 +349,84 @@ hipError_t launch_solve_classes(const double* G, const double* B, const double* 
   return hipGetLastError();
 }
 
-// A = Q A~ on float64 MFMA: one 16x16 output tile per wave, k = i_k.
-template <typename W>
-__global__ void __launch_bounds__(256) backtransform_k(const double* __restrict__ Q,
-                                                       const double* __restrict__ At, int Ik,
-                                                       int s, int64_t spost,
-                                                       double* __restrict__ A64,
-                                                       W* __restrict__ Aw, W* __restrict__ Au) {
+// C = A X for row-major float64 A (M x K) and X (K x N) on float64 MFMA.
+// One 16x16 output tile per workgroup; its four waves take interleaved
+// 4-wide k slices (wave w: k = 4w + 16t .. + 3) with eight slices of loads in
+// flight, and the four partial tiles are summed in a fixed order through LDS.
+// EPI 0 stores C row-major; EPI 1 stores the factor update: folded (eq. 9)
+// into A64 (float64) and Aw (working precision), and row-major into Au.
+template <int EPI, typename W>
+__global__ void __launch_bounds__(256) gemm64_k(const double* __restrict__ A,
+                                                const double* __restrict__ X, int M, int K,
+                                                int N, double* __restrict__ C, int64_t spost,
+                                                double* __restrict__ A64, W* __restrict__ Aw,
+                                                W* __restrict__ Au) {
   typedef Mfma<double> MM;
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int nbj = (s + 15) / 16, nbi = (Ik + 15) / 16;
-  if (t >= nbi * nbj) return;
-  const int i0 = (t / nbj) * 16, j0 = (t % nbj) * 16;
+  __shared__ double part[3][4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nbn = (N + 15) >> 4;
+  const int i0 = (blockIdx.x / nbn) * 16, j0 = (blockIdx.x % nbn) * 16;
   const int kr = lane >> 4, lc = lane & 15;
-  const int ia = i0 + lc, jb = j0 + lc;
+  const bool oka = i0 + lc < M, okb = j0 + lc < N;
+  const int ia = min(i0 + lc, M - 1), jb = min(j0 + lc, N - 1);
   typename MM::acc_t acc = MM::zero();
-  for (int k0 = 0; k0 < Ik; k0 += 4) {
-    const int k = k0 + kr;
-    const double a = (ia < Ik && k < Ik) ? Q[(int64_t)ia * Ik + k] : 0.0;
-    const double b = (k < Ik && jb < s) ? At[(int64_t)k * s + jb] : 0.0;
-    acc = MM::mma(a, b, acc);
+  for (int kb = 4 * wave; kb < K; kb += 128) {
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = kb + 16 * u + kr;
+      const int kc = min(k, K - 1);
+      const double av = A[(int64_t)ia * K + kc], bv = X[(int64_t)kc * N + jb];
+      a[u] = (oka && k < K) ? av : 0.0;
+      b[u] = (okb && k < K) ? bv : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = MM::mma(a[u], b[u], acc);
   }
-  if (jb < s) {
+  if (wave > 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[wave - 1][r][lane] = acc[r];
+  }
+  __syncthreads();
+  if (wave == 0 && okb) {
+    const int j = j0 + lc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = i0 + MM::row(lane, r);
-      if (i < Ik) {
-        const double v = acc[r];
-        const int64_t f = (jb / spost) * ((int64_t)Ik * spost) + (int64_t)i * spost + jb % spost;
-        A64[f] = v;
-        Aw[f] = (W)v;
-        Au[(int64_t)i * s + jb] = (W)v;
+      if (i < M) {
+        const double v = ((acc[r] + part[0][r][lane]) + part[1][r][lane]) + part[2][r][lane];
+        if constexpr (EPI == 0) {
+          C[(int64_t)i * N + j] = v;
+        } else {
+          const int64_t f = (j / spost) * ((int64_t)M * spost) + (int64_t)i * spost + j % spost;
+          A64[f] = v;
+          Aw[f] = (W)v;
+          Au[(int64_t)i * N + j] = (W)v;
+        }
       }
     }
   }
 }
 
+static inline int gemm_blocks(int32_t M, int32_t N) { return ((M + 15) / 16) * ((N + 15) / 16); }
+
+hipError_t launch_project(const double* Qt, const double* B, int32_t Ik, int32_t s, double* Bt,
+                          hipStream_t st) {
+  gemm64_k<0, double><<<gemm_blocks(Ik, s), 256, 0, st>>>(Qt, B, Ik, Ik, s, Bt, 1, nullptr,
+                                                          nullptr, nullptr);
+  return hipGetLastError();
+}
+
 hipError_t launch_backtransform(int prec, const double* Q, const double* At, int32_t Ik,
                                 int32_t s, int64_t spost, double* A64, void* Aw, void* Au,
                                 hipStream_t st) {
-  const int tiles = ((Ik + 15) / 16) * ((s + 15) / 16);
-  const int nb = (tiles + 3) / 4;
+  const int nb = gemm_blocks(Ik, s);
   if (prec == P_F64)
-    backtransform_k<double><<<nb, 256, 0, st>>>(Q, At, Ik, s, spost, A64, (double*)Aw,
-                                                (double*)Au);
+    gemm64_k<1, double><<<nb, 256, 0, st>>>(Q, At, Ik, Ik, s, nullptr, spost, A64,
+                                            (double*)Aw, (double*)Au);
   else
-    backtransform_k<float><<<nb, 256, 0, st>>>(Q, At, Ik, s, spost, A64, (float*)Aw, (float*)Au);
+    gemm64_k<1, float><<<nb, 256, 0, st>>>(Q, At, Ik, Ik, s, nullptr, spost, A64, (float*)Aw,
+                                           (float*)Au);
   return hipGetLastError();
 }
 

@@ -95,9 +95,11 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
                            const GramGeom& g, void* part, hipStream_t st);
 hipError_t launch_reduce_gb(int prec, const GramGeom& g, const void* part, const double* A64,
                             int64_t spost, double rho, double* G, double* B, hipStream_t st);
-hipError_t launch_solve_classes(const double* G, const double* B, const double* Qt,
-                                int32_t Ik, int32_t s, double lam, double delta, double rho,
-                                double* At, double* trace_part, hipStream_t st);
+hipError_t launch_project(const double* Qt, const double* B, int32_t Ik, int32_t s, double* Bt,
+                          hipStream_t st);
+hipError_t launch_solve_classes(const double* G, int32_t Ik, int32_t s, double lam,
+                                double delta, double rho, double* At, double* trace_part,
+                                hipStream_t st);
 hipError_t launch_backtransform(int prec, const double* Q, const double* At, int32_t Ik,
                                 int32_t s, int64_t spost, double* A64, void* Aw, void* Au,
                                 hipStream_t st);

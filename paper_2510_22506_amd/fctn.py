@@ -55,7 +55,7 @@ class fctn_stats(ctypes.Structure):
                 ("objective", ctypes.c_double)]
 
 
-STAGES = ["pair", "gram_rhs", "reduce", "solve", "backtransform", "reconstruct", "x_update",
+STAGES = ["pair", "gram_rhs", "reduce", "solve", "transform", "reconstruct", "x_update",
           "stats"]
 
 

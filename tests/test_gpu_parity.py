@@ -101,6 +101,25 @@ def test_solve_step(prec, dims, ranks):
         assert abs(tr - sylvester.trace_term(Ao, 0.4)) <= 1e-9 * abs(tr)
 
 
+# s_k = R_ka * R_kb at the panel edges of the blocked factorization (1, 31-33,
+# 64, 66, 96, 128, 160, 191, 192) with I_k of both parities and I_k = 1, 2
+SOLVE_EDGES = [
+    ((4, 3, 2), (1, 1, 1)),
+    ((9, 8, 2), (8, 4, 4)),
+    ((7, 10, 1), (11, 3, 6)),
+    ((6, 5, 4), (16, 4, 8)),
+    ((5, 4, 3), (16, 12, 10)),
+    ((3, 2, 2), (191, 1, 1)),
+    ((6, 7, 5), (31, 1, 3)),
+    ((5, 6, 4), (12, 8, 8)),
+]
+
+
+@pytest.mark.parametrize("dims,ranks", SOLVE_EDGES)
+def test_solve_step_panel_edges(dims, ranks):
+    test_solve_step("f64", dims, ranks)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("dims,ranks", SHAPES)
 def test_reconstruct_step(prec, dims, ranks):
