@@ -75,6 +75,26 @@ __device__ inline double bcast_lane(double v, int src) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Value held by lane G of each group of four lanes, for every lane of the
+// group (DPP quad permutation; G is a compile-time constant).
+template <int G>
+__device__ inline double quad_bcast(double v) {
+  constexpr int ctrl = G * 0x55;  // quad_perm [G, G, G, G]
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, ctrl, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), ctrl, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ inline double quad_bcast(double v, int g) {
+  switch (g) {
+    case 0: return quad_bcast<0>(v);
+    case 1: return quad_bcast<1>(v);
+    case 2: return quad_bcast<2>(v);
+    default: return quad_bcast<3>(v);
+  }
+}
+
 // 1/sqrt(d) for d > 0: hardware estimate refined by two Newton steps
 // (quadratic convergence to full double precision).
 __device__ inline double rsqrt_f64(double d) {

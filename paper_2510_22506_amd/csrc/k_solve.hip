@@ -141,10 +141,10 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
     // zero; the pivots live in rdiag only.  After each column the counter
     // *pub is raised (release), so that (b) can follow column by column.
     // (b) rows below the block and the right-hand sides (TRSM), waves 1-3
-    // and 5-15 (SIMD 0 is left to wave 0).  Each row is split over the two
-    // halves of a wave (lanes l and l + 32 hold columns 0-15 and 16-31 of the
-    // same row); a finished value of the first half reaches the second half
-    // by one cross-half shuffle.  Step j waits (acquire) for column j.
+    // and 5-15 (SIMD 0 is left to wave 0).  Two rows per group of four
+    // lanes, eight columns per lane; the finished value of column j reaches
+    // the other lanes of the group by a DPP quad broadcast.  Step j waits
+    // (acquire) for column j.
     const int nbelow = max(s - p0 - 32, 0);
     if (wave == 0) {
       const int i = lane & 31, h = lane >> 5;
@@ -171,41 +171,56 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
         }
       }
     } else if (wave != 4 && (wave - 1 - (wave > 4)) * 32 < nbelow + 2) {
-      const int row = (wave - 1 - (wave > 4)) * 32 + (lane & 31), h = lane >> 5;
-      const bool valid = row < nbelow + 2;
-      const int v = valid ? row - nbelow : 0;
-      double* const base = v < 0 ? pan + p0 + 32 + row : rhs + v * LDP + p0;
-      const int stride = v < 0 ? LDP : 1;
-      double x[16];
+      // rows 2 rp and 2 rp + 1 of the row list (rows below, then the two
+      // right-hand sides) go to the four lanes of quad rp; lane g of the quad
+      // holds their columns 8g .. 8g + 7
+      const int g = lane & 3;
+      const int rp = (wave - 1 - (wave > 4)) * 16 + (lane >> 2);
+      const int nrow = nbelow + 2;
+      const int ra = 2 * rp, rb = 2 * rp + 1;
+      const bool va = ra < nrow, vb = rb < nrow;
+      // row pointers (an absent row reads the first right-hand side)
+      const int ia = va ? ra - nbelow : 0, ib = vb ? rb - nbelow : 0;
+      double* const pa = ia < 0 ? pan + p0 + 32 + ra : rhs + ia * LDP + p0;
+      double* const pb = ib < 0 ? pan + p0 + 32 + rb : rhs + ib * LDP + p0;
+      const int sa = ia < 0 ? LDP : 1, sb = ib < 0 ? LDP : 1;
+      double xa[8], xb[8];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) x[q] = base[(16 * h + q) * stride];
+      for (int q = 0; q < 8; ++q) {
+        xa[q] = pa[(8 * g + q) * sa];
+        xb[q] = pb[(8 * g + q) * sb];
+      }
+      int avail = 0;
 #pragma unroll
       for (int j = 0; j < 32; ++j) {
         if (j < np) {
           // bounded wait: column j is always published (j < np), the bound
           // only guards against a logic error turning into a hang
-          for (int spin = 0; spin < (1 << 16); ++spin) {
-            if (__hip_atomic_load(pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) > j) break;
-            __builtin_amdgcn_s_sleep(1);
+          for (int spin = 0; avail <= j && spin < (1 << 16); ++spin) {
+            avail = __hip_atomic_load(pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (avail <= j) __builtin_amdgcn_s_sleep(1);
           }
-          const int hj = j >> 4, cj = j & 15;
-          const double sc = h == hj ? rdiag[p0 + j] : 1.0;
-          x[cj] *= sc;
-          double xj = x[cj];
-          if (hj == 0) {
-            const double o = __shfl_xor(xj, 32, kWave);
-            xj = h ? o : xj;
-          }
+          const int gj = j >> 3, cj = j & 7;
+          const double sc = g == gj ? rdiag[p0 + j] : 1.0;
+          xa[cj] *= sc;
+          xb[cj] *= sc;
+          const double ya = quad_bcast(xa[cj], gj), yb = quad_bcast(xb[cj], gj);
           // entries at and above the diagonal of column j are stored zeros
 #pragma unroll
-          for (int q = 0; q < 16; ++q) x[q] -= xj * pan[j * LDP + p0 + 16 * h + q];
+          for (int q = 0; q < 8; ++q) {
+            const double l = pan[j * LDP + p0 + 8 * g + q];
+            xa[q] -= ya * l;
+            xb[q] -= yb * l;
+          }
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (valid) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (16 * h + q < np) base[(16 * h + q) * stride] = x[q];
+      for (int q = 0; q < 8; ++q) {
+        if (8 * g + q < np) {
+          if (va) pa[(8 * g + q) * sa] = xa[q];
+          if (vb) pb[(8 * g + q) * sb] = xb[q];
+        }
       }
     }
     __syncthreads();
