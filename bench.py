@@ -13,8 +13,11 @@ alternating factor order).
 Prints ONE JSON line.  `roofline` is for the kernel with the largest summed
 time (HIP events on the plan's stream over the timed region): algorithmic
 flops (or bytes) per launch / average launch time, against MI355X's
-published peak.  `cpu_baseline` is the float64 oracle on the host cores over
-a bounded number of sweeps of the same workload.
+published peak for that kernel's bound.  `serving` is the request-serving
+workload through the continuous-batching server (completions/s, p50/p99
+latency, split bf16 against float32 at saturation).  `cpu_baseline` is the
+float64 oracle on the host cores over a bounded number of sweeps of the same
+workload.
 """
 
 import argparse
@@ -39,6 +42,10 @@ WORKLOADS = {
 }
 DEFAULT_PREC = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f32"}
 MFMA_STAGES = ("gram_rhs", "reconstruct", "pair")
+# bound of every other stage: float64 MFMA products, float64 ALU-latency
+# solves, HBM-bound passes
+F64_MFMA_STAGES = ("transform",)
+ALU_STAGES = ("solve",)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -63,6 +70,96 @@ def measured_traffic(workload, precision, stage):
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def stage_roofline(stage, rec, prec):
+    """Achieved rate of one stage's average launch against the bound of its
+    kernel: algorithmic flops or bytes per launch / average launch time."""
+    n = max(rec["launches"], 1)
+    avg_s = rec["ms"] / 1e3 / n
+    r = {"kernel": stage, "avg_launch_us": avg_s * 1e6, "launches": rec["launches"]}
+    if avg_s <= 0:
+        return r
+    if stage in MFMA_STAGES or stage in F64_MFMA_STAGES or stage in ALU_STAGES:
+        peak = PEAK[prec] if stage in MFMA_STAGES else PEAK["f64"]
+        a = rec["flops"] / n / avg_s
+        r.update({"bound": "alu" if stage in ALU_STAGES else "mfma", "achieved": a / 1e12,
+                  "peak": peak / 1e12, "unit": "TFLOP/s", "frac": a / peak})
+    else:
+        a = rec["bytes"] / n / avg_s
+        r.update({"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
+                  "unit": "GB/s", "frac": a / PEAK["hbm"]})
+    return r
+
+
+def psnr(truth, X):
+    """Mean over the trailing slices of 10 log10(1 / MSE) over the first two
+    modes (pixel values in [0, 1])."""
+    import numpy as np
+    t = truth.reshape(truth.shape[0] * truth.shape[1], -1).astype(np.float64)
+    x = X.reshape(t.shape).astype(np.float64)
+    mse = np.mean((t - x) ** 2, axis=0)
+    return float(np.mean(10.0 * np.log10(1.0 / np.maximum(mse, 1e-30))))
+
+
+def serving(args):
+    """The serving workload: a mix of independent completions (order-3
+    image-shaped {64,128,256}^2 x 3 and order-4 video-shaped 72 x 88 x 3 x
+    {10,25,50}, sampling rates {0.05,0.1,0.2}) through the continuous-batching
+    server.  Poisson arrivals at `serve_rate` in the bf16 served form (split
+    bf16), then saturation runs (every request at t = 0) of the same mix in
+    split bf16 and in float32, with per-request PSNR of the two forms."""
+    import numpy as np
+    import torch
+    from paper_2510_22506_amd import Server, serve
+    from workloads import make_problem, serving_requests
+
+    spec = serving_requests(seed=0, n=args.serve_n, rate=args.serve_rate,
+                            sweeps=args.serve_sweeps)
+    probs = [make_problem(q["config"], seed=q["seed"], dims=q["dims"], sr=q["sr"],
+                          sweeps=q["sweeps"], precision="f32") for q in spec]
+    dev = []
+    for p in probs:
+        dev.append((torch.from_numpy(np.ascontiguousarray(p.Y)).cuda(),
+                    torch.from_numpy(np.ascontiguousarray(p.mask.astype(np.uint8))).cuda(),
+                    torch.from_numpy(np.concatenate([a.ravel() for a in p.A0])).cuda()))
+    torch.cuda.synchronize()
+
+    def requests(prec, idx):
+        return [dict(tag=i, dims=probs[i].dims, ranks=probs[i].ranks, Y=dev[i][0],
+                     mask=dev[i][1], A0=dev[i][2], sweeps=spec[i]["sweeps"], lam=probs[i].lam,
+                     delta=probs[i].delta, rho=probs[i].rho, precision=prec) for i in idx]
+
+    arena = int(min(args.serve_budget, 16 << 30))
+    srv = Server(arena, nstreams=args.serve_streams, max_active=args.serve_active,
+                 depth=args.serve_depth)
+    try:
+        serve.run(srv, requests("bf16x3", range(min(8, len(spec)))))  # warm-up
+        poisson = serve.run(srv, requests("bf16x3", range(len(spec))),
+                            [q["arrival"] for q in spec])
+        sat = {prec: serve.run(srv, requests(prec, range(len(spec))))
+               for prec in ("bf16x3", "f32")}
+    finally:
+        srv.close()
+    dpsnr = []
+    for i, p in enumerate(probs):
+        a = psnr(p.truth, sat["bf16x3"]["done"][i][1].cpu().numpy())
+        b = psnr(p.truth, sat["f32"]["done"][i][1].cpu().numpy())
+        dpsnr.append(a - b)
+    dpsnr = np.abs(np.array(dpsnr))
+    out = {"requests": len(spec), "sweeps_per_request": args.serve_sweeps,
+           "arrival_rate_per_s": args.serve_rate, "form": "bf16x3",
+           "poisson": serve.summarize(poisson),
+           "saturation": {k: serve.summarize(v) for k, v in sat.items()},
+           "psnr_bf16x3_vs_f32_abs_db": {"mean": float(dpsnr.mean()),
+                                         "max": float(dpsnr.max())},
+           "server": {"arena_bytes": arena, "budget_bytes": int(args.serve_budget),
+                      "streams": args.serve_streams, "max_active": args.serve_active,
+                      "depth": args.serve_depth}}
+    out["saturation_speedup_bf16x3_over_f32"] = (
+        out["saturation"]["bf16x3"]["completions_per_s"] /
+        out["saturation"]["f32"]["completions_per_s"])
+    return out
 
 
 def cpu_baseline(prob, sweeps):
@@ -95,6 +192,15 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="add the per-stage breakdown")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-n", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-sweeps", type=int, default=30)
+    ap.add_argument("--serve-budget", type=float, default=200e9,
+                    help="HBM admission budget in bytes (the arena is min(budget, 16 GiB))")
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-active", type=int, default=16)
+    ap.add_argument("--serve-depth", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 256 MiB device-to-device once (a "
                          "kernel of known traffic for scaling HBM byte counters)")
@@ -133,29 +239,12 @@ def main():
     value = args.steps / dt
 
     total_flops = sum(v["flops"] for k, v in prof.items() if k in MFMA_STAGES)
-    dom = max(prof, key=lambda k: prof[k]["ms"])
-    d = prof[dom]
-    avg_s = d["ms"] / 1e3 / max(d["launches"], 1)
-    if dom in MFMA_STAGES:
-        achieved = d["flops"] / max(d["launches"], 1) / avg_s
-        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK[prec]}
-    else:
-        achieved = d["bytes"] / max(d["launches"], 1) / avg_s
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9,
-                "unit": "GB/s", "frac": achieved / PEAK["hbm"]}
-    roof["kernel"] = dom
-    roof["avg_launch_us"] = avg_s * 1e6
-    roof["launches"] = d["launches"]
+    roofs = {k: stage_roofline(k, v, prec) for k, v in prof.items() if v["launches"]}
+    dom = max(roofs, key=lambda k: prof[k]["ms"])
+    roof = dict(roofs[dom])
     roof["traffic"] = measured_traffic(name, prec, dom)
-
-    xp = prof["x_update"]
-    x_avg = xp["ms"] / 1e3 / max(xp["launches"], 1)
-    x_bw = xp["bytes"] / max(xp["launches"], 1) / x_avg if x_avg > 0 else 0.0
-    roof_x = {"bound": "hbm", "kernel": "x_update", "achieved": x_bw / 1e9,
-              "peak": PEAK["hbm"] / 1e9, "unit": "GB/s", "frac": x_bw / PEAK["hbm"],
-              "avg_launch_us": x_avg * 1e6,
-              "traffic": measured_traffic(name, prec, "x_update")}
+    roof_x = dict(roofs["x_update"])
+    roof_x["traffic"] = measured_traffic(name, prec, "x_update")
 
     line = {
         "metric": METRIC,
@@ -181,7 +270,7 @@ def main():
     if args.stages:
         line["stages"] = {k: {"launches": v["launches"], "ms_total": v["ms"],
                               "us_per_launch": v["ms"] * 1e3 / max(v["launches"], 1),
-                              "gflop": v["flops"] / 1e9}
+                              "gflop": v["flops"] / 1e9, "roofline": roofs[k]}
                           for k, v in prof.items() if v["launches"]}
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
@@ -190,6 +279,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         line["calibration_copy_bytes"] = src.numel() * 4
+    if not args.no_serve:
+        try:
+            line["serving"] = serving(args)
+        except Exception as e:  # reported, never hides the sweep measurement
+            line["serving"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_sweeps)
     print(json.dumps(line), flush=True)

@@ -113,6 +113,12 @@ fctn_status fctn_plan(const fctn_desc* desc, void* ws_dev, size_t ws_bytes,
  * the round-to-nearest-even cast. */
 fctn_status fctn_set_factors(fctn_plan_t plan, const double* const* A_host);
 
+/* Initial factors from device memory: A_dev holds factor 1, factor 2, ..,
+ * factor N in float64, each with the factor layout above, back to back.
+ * Asynchronous on the plan's stream (A_dev must stay valid until the copy
+ * has run). */
+fctn_status fctn_set_factors_dev(fctn_plan_t plan, const double* A_dev);
+
 /* Observed data (Algorithm 1: X^(1) = Y, read as P_Omega(Y)).  Y_dev: elem
  * tensor; mask_dev: uint8 tensor, nonzero = observed.  Values of Y off Omega
  * are never read into arithmetic (they may be NaN).  Y and mask are copied
@@ -186,6 +192,71 @@ fctn_status fctn_step_x_update(fctn_plan_t plan, const void* Z_dev,
 /* Sizes of the plan's unfoldings for mode k: s_k and I_k. */
 fctn_status fctn_mode_sizes(const fctn_desc* desc, int32_t k, int64_t* s_k,
                             int64_t* I_k);
+
+/* ---- serving: continuous batching of independent completions -------------
+ * A server keeps many completions (each one plan, as above) resident at once
+ * and runs their sweeps concurrently.  It owns no memory of its own on the
+ * device: every admitted request's plan is carved from the caller's arena, so
+ * admission is by exact memory footprint (fctn_workspace_bytes).  Requests
+ * are admitted first in first out whenever a slot (max_active) and arena
+ * room are free; each admitted request's sweeps go to one of the caller's
+ * streams (round robin), at most `depth` of them queued at a time, one
+ * sweep per request per round, so requests that share a stream interleave
+ * and requests on different streams overlap on the device.  A request's
+ * result is that of fctn_plan + fctn_set_factors_dev + fctn_set_observed +
+ * fctn_sweep(sweeps) on it alone, bit for bit: the plans share no state and
+ * every kernel is deterministic.  The server is driven by fctn_server_step,
+ * which never blocks; calls on one server are not thread-safe. */
+typedef struct fctn_server_s* fctn_server_t;
+
+typedef struct {
+  fctn_desc desc;           /* the completion problem                         */
+  const void* Y_dev;        /* observed tensor, elem (see conventions)        */
+  const uint8_t* mask_dev;  /* uint8, nonzero = observed                      */
+  const double* A0_dev;     /* initial factors, as for fctn_set_factors_dev   */
+  void* X_out_dev;          /* receives the completed X (elem tensor)         */
+  int32_t sweeps;           /* fixed number of PAM sweeps (>= 0)              */
+  uint64_t tag;             /* caller's identifier, returned on completion    */
+} fctn_request;
+/* Y_dev, mask_dev, A0_dev and X_out_dev must stay valid until the request's
+ * completion has been returned. */
+
+typedef struct {
+  uint64_t tag;
+  int32_t status;           /* FCTN_OK, or FCTN_E_NUMERIC: a non-finite
+                               observed value (the sweeps still ran)          */
+  int32_t sweeps_done;
+  double rel_change;        /* of the last sweep (eq. 10 stopping quantity)   */
+  double objective;         /* f after the last sweep (Section 3.5)           */
+  double t_submit, t_admit, t_done;  /* host CLOCK_MONOTONIC, seconds        */
+} fctn_completion;
+
+/* arena_dev: caller-owned device buffer, 256-byte aligned, the memory budget
+ * of all admitted requests together; streams: nstreams hipStream_t handles;
+ * max_active >= 1 requests resident at once; depth >= 1 sweeps queued per
+ * request.  Allocates pinned host memory for the completion scalars. */
+fctn_status fctn_server_create(void* arena_dev, size_t arena_bytes,
+                               void* const* streams, int32_t nstreams,
+                               int32_t max_active, int32_t depth,
+                               fctn_server_t* out);
+
+/* Queue a request (copied).  FCTN_E_NOMEM if its footprint exceeds the
+ * whole arena (it could never be admitted); FCTN_E_INVALID /
+ * FCTN_E_UNSUPPORTED for a descriptor fctn_plan would reject. */
+fctn_status fctn_server_submit(fctn_server_t server, const fctn_request* req);
+
+/* Non-blocking progress: retire finished requests (their X has been copied
+ * out) into done[0 .. *n_done) (at most max_done), admit queued requests,
+ * and queue further sweeps of the admitted ones. */
+fctn_status fctn_server_step(fctn_server_t server, fctn_completion* done,
+                             int32_t max_done, int32_t* n_done);
+
+/* Queue length, resident requests and arena bytes in use (any may be NULL). */
+fctn_status fctn_server_query(fctn_server_t server, int32_t* queued,
+                              int32_t* active, size_t* arena_used);
+
+/* Waits for all of the server's streams, then releases its host state. */
+fctn_status fctn_server_destroy(fctn_server_t server);
 
 /* ---- per-kernel timing ---------------------------------------------------
  * Stages, one per kernel of a sweep: */

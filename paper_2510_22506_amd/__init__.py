@@ -6,6 +6,7 @@ loop on top of it.
 """
 
 from .fctn import (  # noqa: F401
-    Plan, FctnError, make_desc, fctn_workspace_bytes, fctn_mode_sizes, fctn_status_str,
+    Plan, Server, FctnError, make_desc, fctn_workspace_bytes, fctn_mode_sizes, fctn_status_str,
     sweep_many, factor_shape, lib, LIB_PATH,
 )
+from . import serve  # noqa: F401

@@ -1,13 +1,16 @@
 // Host side of libfctn.so: descriptor validation, workspace carving, the
 // per-mode operand tables, the sweep scheduler (Algorithms 1-2, including the
-// pair-tensor cache of the reuse mechanism and the alternating factor order)
-// and the C ABI declared in fctn.h.
+// pair-tensor cache of the reuse mechanism and the alternating factor order),
+// the continuous-batching server and the C ABI declared in fctn.h.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #include <algorithm>
+#include <deque>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -75,6 +78,7 @@ struct fctn_plan_s {
   void* Z;
   uint32_t* bits;
   int32_t* bad_part;
+  int32_t* bad_flag;
   int bad_nblk;
   double* A64[4];
   void* Aw[4];
@@ -400,6 +404,7 @@ size_t carve(fctn_plan_s* P, char* base) {
   P->bits = (uint32_t*)c.take(((P->numel + 63) / 64) * 2 * sizeof(uint32_t));
   P->bad_nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (P->numel + 255) / 256));
   P->bad_part = (int32_t*)c.take(P->bad_nblk * sizeof(int32_t));
+  P->bad_flag = (int32_t*)c.take(sizeof(int32_t));
   int64_t smax = 1, imax = 1;
   P->max_cls = 1;
   size_t part_bytes = 0;
@@ -650,6 +655,77 @@ fctn_status read_slot(fctn_plan_s* P, const double* slot, fctn_sweep_stats* out)
   return FCTN_OK;
 }
 
+// Plan set-up without host synchronization or pageable copies, so that it
+// can be queued on a stream that other plans are using.
+fctn_status plan_build(const fctn_desc* desc, void* ws_dev, size_t ws_bytes, hipStream_t st,
+                       fctn_plan_s** out) {
+  *out = nullptr;
+  fctn_status v = validate(desc);
+  if (v != FCTN_OK) return v;
+  if (!ws_dev || ((uintptr_t)ws_dev & 255)) return FCTN_E_INVALID;
+  fctn_plan_s* P = new (std::nothrow) fctn_plan_s;
+  if (!P) return FCTN_E_NOMEM;
+  if (!init_plan_struct(desc, P)) {
+    delete P;
+    return FCTN_E_UNSUPPORTED;
+  }
+  const size_t need = carve(P, nullptr);
+  if (ws_bytes < need) {
+    delete P;
+    return FCTN_E_NOMEM;
+  }
+  carve(P, (char*)ws_dev);
+  P->st = st;
+  const char* dbg = getenv("FCTN_DEBUG");
+  P->debug = dbg && dbg[0] == '1';
+  // zero state, bases, per-mode constants
+  bool ok = hipMemsetAsync(ws_dev, 0, need, P->st) == hipSuccess;
+  PlanConsts pc{};
+  pc.n = P->N;
+  for (int k = 0; k < P->N && ok; ++k) {
+    ok = launch_build_basis(P->Q[k], P->Qt[k], P->lamcol[k], (int32_t)P->mode[k].Ik,
+                            desc->delta[k], P->st) == hipSuccess;
+    pc.lam_half[k] = 0.5 * desc->lambda[k];
+    pc.ncls[k] = P->mode[k].ncls;
+  }
+  ok = ok && launch_set_consts(P->lam_half, P->ncls_dev, pc, P->st) == hipSuccess;
+  if (!ok) {
+    delete P;
+    return FCTN_E_DEVICE;
+  }
+  *out = P;
+  return FCTN_OK;
+}
+
+// float64 factors from device memory (concatenated in mode order), then the
+// working-precision copies; asynchronous on the plan's stream
+fctn_status set_factors_dev(fctn_plan_s* P, const double* A_dev) {
+  int64_t off = 0;
+  for (int k = 0; k < P->N; ++k) {
+    if (hipMemcpyAsync(P->A64[k], A_dev + off, P->fnum[k] * sizeof(double),
+                       hipMemcpyDeviceToDevice, P->st) != hipSuccess) {
+      P->sticky = FCTN_E_DEVICE;
+      return FCTN_E_DEVICE;
+    }
+    off += P->fnum[k];
+    const ModeInfo& m = P->mode[k];
+    FCTN_LAUNCH(P, launch_cast_factor(P->prec, P->A64[k], P->Aw[k], P->Au[k], (int32_t)m.Ik,
+                                      (int32_t)m.s, m.spost, P->st));
+    P->fver[k]++;
+  }
+  P->pvalid[0] = P->pvalid[1] = false;
+  return FCTN_OK;
+}
+
+// X = P_Omega(Y), the mask bits and the non-finite flag (P->bad_flag[0]);
+// asynchronous on the plan's stream
+fctn_status set_observed_async(fctn_plan_s* P, const void* Y_dev, const uint8_t* mask_dev) {
+  FCTN_LAUNCH(P, launch_init_observed(P->prec, Y_dev, mask_dev, P->X, P->bits, P->bad_part,
+                                      P->numel, P->bad_nblk, P->st));
+  FCTN_LAUNCH(P, launch_any_flag(P->bad_part, P->bad_nblk, P->bad_flag, P->st));
+  return FCTN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -682,40 +758,10 @@ fctn_status fctn_plan(const fctn_desc* desc, void* ws_dev, size_t ws_bytes, void
                       fctn_plan_t* out) {
   if (!out) return FCTN_E_INVALID;
   *out = nullptr;
-  fctn_status v = validate(desc);
+  fctn_plan_s* P = nullptr;
+  fctn_status v = plan_build(desc, ws_dev, ws_bytes, (hipStream_t)hip_stream, &P);
   if (v != FCTN_OK) return v;
-  if (!ws_dev || ((uintptr_t)ws_dev & 255)) return FCTN_E_INVALID;
-  fctn_plan_s* P = new (std::nothrow) fctn_plan_s;
-  if (!P) return FCTN_E_NOMEM;
-  if (!init_plan_struct(desc, P)) {
-    delete P;
-    return FCTN_E_UNSUPPORTED;
-  }
-  const size_t need = carve(P, nullptr);
-  if (ws_bytes < need) {
-    delete P;
-    return FCTN_E_NOMEM;
-  }
-  carve(P, (char*)ws_dev);
-  P->st = (hipStream_t)hip_stream;
-  const char* dbg = getenv("FCTN_DEBUG");
-  P->debug = dbg && dbg[0] == '1';
-  // zero state, bases, per-mode constants
-  bool ok = hipMemsetAsync(ws_dev, 0, need, P->st) == hipSuccess;
-  std::vector<double> lh(P->N);
-  std::vector<int32_t> nc(P->N);
-  for (int k = 0; k < P->N && ok; ++k) {
-    ok = launch_build_basis(P->Q[k], P->Qt[k], P->lamcol[k], (int32_t)P->mode[k].Ik,
-                            desc->delta[k], P->st) == hipSuccess;
-    lh[k] = 0.5 * desc->lambda[k];
-    nc[k] = P->mode[k].ncls;
-  }
-  ok = ok && hipMemcpyAsync(P->lam_half, lh.data(), P->N * sizeof(double),
-                            hipMemcpyHostToDevice, P->st) == hipSuccess;
-  ok = ok && hipMemcpyAsync(P->ncls_dev, nc.data(), P->N * sizeof(int32_t),
-                            hipMemcpyHostToDevice, P->st) == hipSuccess;
-  ok = ok && hipStreamSynchronize(P->st) == hipSuccess;
-  if (!ok) {
+  if (hipStreamSynchronize(P->st) != hipSuccess) {
     delete P;
     return FCTN_E_DEVICE;
   }
@@ -750,18 +796,22 @@ fctn_status fctn_set_factors(fctn_plan_t P, const double* const* A_host) {
 fctn_status fctn_set_observed(fctn_plan_t P, const void* Y_dev, const uint8_t* mask_dev) {
   if (!P || !Y_dev || !mask_dev) return FCTN_E_INVALID;
   if (P->sticky != FCTN_OK) return P->sticky;
-  FCTN_LAUNCH(P, launch_init_observed(P->prec, Y_dev, mask_dev, P->X, P->bits, P->bad_part,
-                                      P->numel, P->bad_nblk, P->st));
-  std::vector<int32_t> bad(P->bad_nblk);
-  if (hipMemcpyAsync(bad.data(), P->bad_part, bad.size() * sizeof(int32_t),
-                     hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+  fctn_status v = set_observed_async(P, Y_dev, mask_dev);
+  if (v != FCTN_OK) return v;
+  int32_t bad = 0;
+  if (hipMemcpyAsync(&bad, P->bad_flag, sizeof(bad), hipMemcpyDeviceToHost, P->st) !=
+          hipSuccess ||
       hipStreamSynchronize(P->st) != hipSuccess) {
     P->sticky = FCTN_E_DEVICE;
     return FCTN_E_DEVICE;
   }
-  for (int32_t b : bad)
-    if (b) return FCTN_E_NUMERIC;
-  return FCTN_OK;
+  return bad ? FCTN_E_NUMERIC : FCTN_OK;
+}
+
+fctn_status fctn_set_factors_dev(fctn_plan_t P, const double* A_dev) {
+  if (!P || !A_dev) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  return set_factors_dev(P, A_dev);
 }
 
 fctn_status fctn_set_x(fctn_plan_t P, const void* X_dev) {
@@ -997,6 +1047,316 @@ const char* fctn_status_str(fctn_status s) {
     case FCTN_E_UNSUPPORTED: return "unsupported configuration";
   }
   return "unknown status";
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Continuous batching: independent completions share one GPU.  Each admitted
+// request is a plan carved from the server's arena; its sweeps are queued on
+// one of the caller's streams, at most `depth` at a time, one sweep per
+// request per round so that requests sharing a stream interleave.  Requests
+// are admitted first-in first-out as slots and arena room free up.
+// ---------------------------------------------------------------------------
+namespace {
+
+double mono_now() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+struct SrvPending {
+  fctn_request r;
+  size_t bytes;
+  double t_submit;
+};
+
+struct SrvSlot {
+  bool busy = false;
+  bool finishing = false;
+  fctn_plan_s* plan = nullptr;
+  size_t off = 0, bytes = 0;
+  int32_t enq = 0;
+  std::deque<hipEvent_t> inflight;
+  hipEvent_t done = nullptr;
+  fctn_request req{};
+  double t_submit = 0.0, t_admit = 0.0;
+};
+
+}  // namespace
+
+struct fctn_server_s {
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  std::map<size_t, size_t> free_;  // offset -> bytes; disjoint, coalesced
+  size_t used = 0;
+  std::vector<hipStream_t> streams;
+  int next_stream = 0;
+  int depth = 1;
+  std::vector<SrvSlot> slots;
+  std::deque<SrvPending> queue;
+  std::vector<hipEvent_t> pool;
+  int32_t* pin_flag = nullptr;  // pinned host memory, one flag per slot
+  double* pin_stats = nullptr;  // pinned host memory, four doubles per slot
+  fctn_status sticky = FCTN_OK;
+};
+
+namespace {
+
+bool arena_alloc(fctn_server_s* S, size_t bytes, size_t* off) {
+  for (auto it = S->free_.begin(); it != S->free_.end(); ++it) {
+    if (it->second < bytes) continue;
+    *off = it->first;
+    const size_t rest = it->second - bytes;
+    S->free_.erase(it);
+    if (rest > 0) S->free_[*off + bytes] = rest;
+    S->used += bytes;
+    return true;
+  }
+  return false;
+}
+
+void arena_free(fctn_server_s* S, size_t off, size_t bytes) {
+  S->used -= bytes;
+  auto it = S->free_.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != S->free_.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    S->free_.erase(nx);
+  }
+  if (it != S->free_.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      S->free_.erase(it);
+    }
+  }
+}
+
+hipEvent_t srv_event(fctn_server_s* S) {
+  if (!S->pool.empty()) {
+    hipEvent_t e = S->pool.back();
+    S->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+fctn_status srv_fail(fctn_server_s* S, fctn_status v) {
+  S->sticky = v;
+  return v;
+}
+
+// set-up of an admitted request on stream st (no host synchronization)
+fctn_status srv_admit(fctn_server_s* S, int slot, const SrvPending& h, size_t off,
+                      hipStream_t st) {
+  fctn_plan_s* P = nullptr;
+  fctn_status v = plan_build(&h.r.desc, S->arena + off, h.bytes, st, &P);
+  if (v != FCTN_OK) return v;
+  v = set_factors_dev(P, h.r.A0_dev);
+  if (v == FCTN_OK) v = set_observed_async(P, h.r.Y_dev, h.r.mask_dev);
+  if (v == FCTN_OK && hipMemcpyAsync(S->pin_flag + slot, P->bad_flag, sizeof(int32_t),
+                                     hipMemcpyDeviceToHost, st) != hipSuccess)
+    v = FCTN_E_DEVICE;
+  if (v != FCTN_OK) {
+    delete P;
+    return v;
+  }
+  SrvSlot& sl = S->slots[slot];
+  sl.busy = true;
+  sl.finishing = false;
+  sl.plan = P;
+  sl.off = off;
+  sl.bytes = h.bytes;
+  sl.enq = 0;
+  sl.req = h.r;
+  sl.t_submit = h.t_submit;
+  sl.t_admit = mono_now();
+  return FCTN_OK;
+}
+
+// results of a request whose sweeps are all queued: X out, last-sweep
+// scalars to pinned memory, then the completion event
+fctn_status srv_finish(fctn_server_s* S, int slot) {
+  SrvSlot& sl = S->slots[slot];
+  fctn_plan_s* P = sl.plan;
+  if (hipMemcpyAsync(sl.req.X_out_dev, P->X, P->numel * P->es, hipMemcpyDeviceToDevice,
+                     P->st) != hipSuccess)
+    return FCTN_E_DEVICE;
+  double* ps = S->pin_stats + 4 * slot;
+  if (P->sweeps_done > 0) {
+    if (hipMemcpyAsync(ps, P->hist + ((P->sweeps_done - 1) % kHist) * 4, 4 * sizeof(double),
+                       hipMemcpyDeviceToHost, P->st) != hipSuccess)
+      return FCTN_E_DEVICE;
+  } else {
+    ps[0] = ps[1] = ps[2] = ps[3] = 0.0;
+  }
+  sl.done = srv_event(S);
+  if (!sl.done || hipEventRecord(sl.done, P->st) != hipSuccess) return FCTN_E_DEVICE;
+  sl.finishing = true;
+  return FCTN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fctn_status fctn_server_create(void* arena_dev, size_t arena_bytes, void* const* streams,
+                               int32_t nstreams, int32_t max_active, int32_t depth,
+                               fctn_server_t* out) {
+  if (!out) return FCTN_E_INVALID;
+  *out = nullptr;
+  if (!arena_dev || ((uintptr_t)arena_dev & 255) || arena_bytes < 256 || !streams ||
+      nstreams < 1 || max_active < 1 || depth < 1)
+    return FCTN_E_INVALID;
+  fctn_server_s* S = new (std::nothrow) fctn_server_s;
+  if (!S) return FCTN_E_NOMEM;
+  S->arena = (char*)arena_dev;
+  S->arena_bytes = arena_bytes & ~(size_t)255;
+  S->free_[0] = S->arena_bytes;
+  for (int i = 0; i < nstreams; ++i) S->streams.push_back((hipStream_t)streams[i]);
+  S->depth = depth;
+  S->slots.resize(max_active);
+  if (hipHostMalloc((void**)&S->pin_flag, sizeof(int32_t) * max_active, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&S->pin_stats, sizeof(double) * 4 * max_active,
+                    hipHostMallocDefault) != hipSuccess) {
+    if (S->pin_flag) hipHostFree(S->pin_flag);
+    delete S;
+    return FCTN_E_DEVICE;
+  }
+  *out = S;
+  return FCTN_OK;
+}
+
+fctn_status fctn_server_submit(fctn_server_t S, const fctn_request* r) {
+  if (!S || !r) return FCTN_E_INVALID;
+  if (S->sticky != FCTN_OK) return S->sticky;
+  fctn_status v = validate(&r->desc);
+  if (v != FCTN_OK) return v;
+  if (!r->Y_dev || !r->mask_dev || !r->A0_dev || !r->X_out_dev || r->sweeps < 0)
+    return FCTN_E_INVALID;
+  const size_t bytes = align256(fctn_workspace_bytes(&r->desc));
+  if (bytes == 0) return FCTN_E_UNSUPPORTED;
+  if (bytes > S->arena_bytes) return FCTN_E_NOMEM;
+  S->queue.push_back(SrvPending{*r, bytes, mono_now()});
+  return FCTN_OK;
+}
+
+fctn_status fctn_server_step(fctn_server_t S, fctn_completion* done, int32_t max_done,
+                             int32_t* n_done) {
+  if (!S || !n_done || max_done < 0 || (max_done > 0 && !done)) return FCTN_E_INVALID;
+  *n_done = 0;
+  if (S->sticky != FCTN_OK) return S->sticky;
+  const int ns = (int)S->slots.size();
+  // retire
+  for (int i = 0; i < ns && *n_done < max_done; ++i) {
+    SrvSlot& sl = S->slots[i];
+    if (!sl.busy || !sl.finishing) continue;
+    const hipError_t q = hipEventQuery(sl.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return srv_fail(S, FCTN_E_DEVICE);
+    fctn_completion& c = done[(*n_done)++];
+    c.tag = sl.req.tag;
+    c.status = S->pin_flag[i] ? FCTN_E_NUMERIC : FCTN_OK;
+    c.sweeps_done = sl.enq;
+    c.rel_change = S->pin_stats[4 * i + 0];
+    c.objective = S->pin_stats[4 * i + 3];
+    c.t_submit = sl.t_submit;
+    c.t_admit = sl.t_admit;
+    c.t_done = mono_now();
+    S->pool.push_back(sl.done);
+    sl.done = nullptr;
+    for (hipEvent_t e : sl.inflight) S->pool.push_back(e);
+    sl.inflight.clear();
+    delete sl.plan;
+    sl.plan = nullptr;
+    arena_free(S, sl.off, sl.bytes);
+    sl.busy = sl.finishing = false;
+  }
+  // admit, first in first out: the head of the queue waits for room
+  while (!S->queue.empty()) {
+    int slot = -1;
+    for (int i = 0; i < ns; ++i)
+      if (!S->slots[i].busy) {
+        slot = i;
+        break;
+      }
+    if (slot < 0) break;
+    const SrvPending& h = S->queue.front();
+    size_t off = 0;
+    if (!arena_alloc(S, h.bytes, &off)) break;
+    hipStream_t st = S->streams[S->next_stream];
+    S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
+    fctn_status v = srv_admit(S, slot, h, off, st);
+    if (v != FCTN_OK) {
+      arena_free(S, off, h.bytes);
+      return srv_fail(S, v);
+    }
+    S->queue.pop_front();
+  }
+  // progress: rounds of one sweep per request until every request has
+  // `depth` sweeps in flight or all of its sweeps queued
+  for (bool more = true; more;) {
+    more = false;
+    for (int i = 0; i < ns; ++i) {
+      SrvSlot& sl = S->slots[i];
+      if (!sl.busy || sl.finishing) continue;
+      while (!sl.inflight.empty()) {
+        const hipError_t q = hipEventQuery(sl.inflight.front());
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) return srv_fail(S, FCTN_E_DEVICE);
+        S->pool.push_back(sl.inflight.front());
+        sl.inflight.pop_front();
+      }
+      if ((int)sl.inflight.size() < S->depth && sl.enq < sl.req.sweeps) {
+        fctn_status v = one_sweep(sl.plan);
+        if (v != FCTN_OK) return srv_fail(S, v);
+        hipEvent_t e = srv_event(S);
+        if (!e || hipEventRecord(e, sl.plan->st) != hipSuccess)
+          return srv_fail(S, FCTN_E_DEVICE);
+        sl.inflight.push_back(e);
+        sl.enq++;
+        more = true;
+      }
+      if (sl.enq == sl.req.sweeps) {
+        fctn_status v = srv_finish(S, i);
+        if (v != FCTN_OK) return srv_fail(S, v);
+      }
+    }
+  }
+  return FCTN_OK;
+}
+
+fctn_status fctn_server_query(fctn_server_t S, int32_t* queued, int32_t* active,
+                              size_t* arena_used) {
+  if (!S) return FCTN_E_INVALID;
+  if (queued) *queued = (int32_t)S->queue.size();
+  if (active) {
+    int32_t a = 0;
+    for (const SrvSlot& sl : S->slots) a += sl.busy ? 1 : 0;
+    *active = a;
+  }
+  if (arena_used) *arena_used = S->used;
+  return S->sticky;
+}
+
+fctn_status fctn_server_destroy(fctn_server_t S) {
+  if (!S) return FCTN_E_INVALID;
+  for (hipStream_t st : S->streams) hipStreamSynchronize(st);
+  for (SrvSlot& sl : S->slots) {
+    for (hipEvent_t e : sl.inflight) hipEventDestroy(e);
+    if (sl.done) hipEventDestroy(sl.done);
+    delete sl.plan;
+  }
+  for (hipEvent_t e : S->pool) hipEventDestroy(e);
+  hipHostFree(S->pin_flag);
+  hipHostFree(S->pin_stats);
+  delete S;
+  return FCTN_OK;
 }
 
 }  // extern "C"

@@ -53,6 +53,34 @@ hipError_t launch_init_observed(int prec, const void* Y, const uint8_t* mask, vo
   return hipGetLastError();
 }
 
+__global__ void set_consts_k(double* __restrict__ lam_half, int32_t* __restrict__ ncls,
+                             PlanConsts c) {
+  const int t = threadIdx.x;
+  if (t < c.n) {
+    lam_half[t] = c.lam_half[t];
+    ncls[t] = c.ncls[t];
+  }
+}
+
+hipError_t launch_set_consts(double* lam_half, int32_t* ncls, const PlanConsts& c,
+                             hipStream_t st) {
+  set_consts_k<<<1, 64, 0, st>>>(lam_half, ncls, c);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) any_flag_k(const int32_t* __restrict__ part, int n,
+                                                  int32_t* __restrict__ flag) {
+  int v = 0;
+  for (int i = threadIdx.x; i < n; i += 256) v |= part[i];
+  v = __syncthreads_or(v);
+  if (threadIdx.x == 0) flag[0] = v ? 1 : 0;
+}
+
+hipError_t launch_any_flag(const int32_t* part, int n, int32_t* flag, hipStream_t st) {
+  any_flag_k<<<1, 256, 0, st>>>(part, n, flag);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // working-precision copies of a float64 factor (round to nearest even): Aw in
 // the factor layout and Au as the row-major mode-k unfolding (I_k x s_k)

@@ -83,6 +83,18 @@ struct PairDesc {
 // precision codes shared with the C ABI
 enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
 
+// per-mode constants of a plan, passed by value to the kernel that stores them
+struct PlanConsts {
+  double lam_half[8];
+  int32_t ncls[8];
+  int32_t n;
+};
+
+hipError_t launch_set_consts(double* lam_half, int32_t* ncls, const PlanConsts& c,
+                             hipStream_t st);
+// flag[0] = OR of part[0 .. n)
+hipError_t launch_any_flag(const int32_t* part, int n, int32_t* flag, hipStream_t st);
+
 hipError_t launch_init_observed(int prec, const void* Y, const uint8_t* mask, void* X,
                                 uint32_t* bits, int32_t* bad_part, int64_t n, int nblk,
                                 hipStream_t st);

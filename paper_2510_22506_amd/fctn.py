@@ -68,6 +68,22 @@ class fctn_profile(ctypes.Structure):
                        "bytes": self.bytes[i]} for i, name in enumerate(STAGES)}
 
 
+class fctn_request(ctypes.Structure):
+    _fields_ = [("desc", fctn_desc), ("Y_dev", ctypes.c_void_p), ("mask_dev", ctypes.c_void_p),
+                ("A0_dev", ctypes.c_void_p), ("X_out_dev", ctypes.c_void_p),
+                ("sweeps", ctypes.c_int32), ("tag", ctypes.c_uint64)]
+
+
+class fctn_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("sweeps_done", ctypes.c_int32), ("rel_change", ctypes.c_double),
+                ("objective", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 _lib = None
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(fctn_desc)
@@ -76,6 +92,7 @@ _SIGS = {
     "fctn_plan": (ctypes.c_int, [_D, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
     "fctn_set_factors": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]),
     "fctn_set_observed": (ctypes.c_int, [_P, _P, _P]),
+    "fctn_set_factors_dev": (ctypes.c_int, [_P, _P]),
     "fctn_set_x": (ctypes.c_int, [_P, _P]),
     "fctn_sweep": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(fctn_sweep_stats)]),
     "fctn_sweep_many": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32]),
@@ -95,6 +112,15 @@ _SIGS = {
     "fctn_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(fctn_profile), ctypes.c_int32]),
     "fctn_destroy": (ctypes.c_int, [_P]),
     "fctn_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "fctn_server_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(_P), ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "fctn_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(fctn_request)]),
+    "fctn_server_step": (ctypes.c_int, [_P, ctypes.POINTER(fctn_completion), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "fctn_server_query": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "fctn_server_destroy": (ctypes.c_int, [_P]),
 }
 
 
@@ -194,6 +220,12 @@ class Plan:
         ptrs = (ctypes.POINTER(ctypes.c_double) * len(arrs))(
             *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs])
         _check(lib().fctn_set_factors(self.handle, ptrs), "fctn_set_factors")
+
+    def set_factors_dev(self, A_dev):
+        """A_dev: float64 device tensor holding every factor back to back."""
+        self._keep_A = A_dev
+        self._sync_inputs()
+        _check(lib().fctn_set_factors_dev(self.handle, _ptr(A_dev)), "fctn_set_factors_dev")
 
     def set_observed(self, Y, mask):
         Y = self._dev(Y, self.elem)
@@ -326,3 +358,74 @@ def factor_shape(dims, ranks, k):
 def sweep_many(plans, nsweeps):
     arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
     _check(lib().fctn_sweep_many(arr, len(plans), int(nsweeps)), "fctn_sweep_many")
+
+
+class Server:
+    """Continuous-batching server (fctn_server_*): a torch-owned arena as the
+    memory budget, `nstreams` torch streams of default priority, at most
+    `max_active` resident requests with `depth` sweeps queued each."""
+
+    def __init__(self, arena_bytes, nstreams=4, max_active=16, depth=2, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.arena_bytes = int(arena_bytes) // 256 * 256
+        self.arena = torch.empty(self.arena_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.arena.data_ptr()
+        self.base = (base + 255) // 256 * 256
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(nstreams)]
+        handles = (ctypes.c_void_p * nstreams)(*[s.cuda_stream for s in self.streams])
+        h = ctypes.c_void_p()
+        _check(lib().fctn_server_create(ctypes.c_void_p(self.base), self.arena_bytes, handles,
+                                        nstreams, max_active, depth, ctypes.byref(h)),
+               "fctn_server_create")
+        self.handle = h
+        self.keep = {}
+        self._done = (fctn_completion * 256)()
+
+    def submit(self, tag, dims, ranks, Y, mask, A0, sweeps, lam=1e-2, delta=0.5, rho=0.1,
+               precision="bf16x3", reuse=True, order_policy=1):
+        """Queue a request.  Y, mask: device tensors (elem, uint8); A0: float64
+        device tensor with every factor back to back.  The completed X is
+        returned by step() in a tensor allocated here."""
+        torch = self.torch
+        desc = make_desc(dims, ranks, lam, delta, rho, precision, reuse, order_policy)
+        elem = torch.float64 if precision == "f64" else torch.float32
+        X = torch.empty(tuple(int(d) for d in dims), dtype=elem, device=self.device)
+        req = fctn_request()
+        req.desc = desc
+        req.Y_dev = Y.data_ptr()
+        req.mask_dev = mask.data_ptr()
+        req.A0_dev = A0.data_ptr()
+        req.X_out_dev = X.data_ptr()
+        req.sweeps = int(sweeps)
+        req.tag = int(tag)
+        # inputs prepared on torch's current stream must be complete before
+        # the server's streams read them
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().fctn_server_submit(self.handle, ctypes.byref(req)), "fctn_server_submit")
+        self.keep[int(tag)] = (Y, mask, A0, X)
+
+    def step(self):
+        """Non-blocking progress; returns a list of (completion dict, X tensor)."""
+        n = ctypes.c_int32()
+        _check(lib().fctn_server_step(self.handle, self._done, len(self._done), ctypes.byref(n)),
+               "fctn_server_step")
+        out = []
+        for i in range(n.value):
+            c = self._done[i].as_dict()
+            out.append((c, self.keep.pop(c["tag"])[3]))
+        return out
+
+    def query(self):
+        q = ctypes.c_int32()
+        a = ctypes.c_int32()
+        u = ctypes.c_size_t()
+        _check(lib().fctn_server_query(self.handle, ctypes.byref(q), ctypes.byref(a),
+                                       ctypes.byref(u)), "fctn_server_query")
+        return q.value, a.value, u.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            lib().fctn_server_destroy(self.handle)
+            self.handle = None
