@@ -81,7 +81,12 @@ def stage_roofline(stage, rec, prec):
     if avg_s <= 0:
         return r
     if stage in MFMA_STAGES or stage in F64_MFMA_STAGES or stage in ALU_STAGES:
-        peak = PEAK[prec] if stage in MFMA_STAGES else PEAK["f64"]
+        if stage == "gram_rhs":
+            peak = PEAK[prec]          # bf16 forms run their Gram / RHS on bf16 MFMA
+        elif stage in MFMA_STAGES:
+            peak = PEAK["f64"] if prec == "f64" else PEAK["f32"]   # float32 MFMA otherwise
+        else:
+            peak = PEAK["f64"]
         a = rec["flops"] / n / avg_s
         r.update({"bound": "alu" if stage in ALU_STAGES else "mfma", "achieved": a / 1e12,
                   "peak": peak / 1e12, "unit": "TFLOP/s", "frac": a / peak})

@@ -303,7 +303,9 @@ bool choose_tile(const MGen& mg, int mg_repeat, int kalign, Extra extra_mfma, Ld
       const double v_per_tile = tg.nTileV > 1 ? (double)tg.Kp * tg.Qp : 0.0;
       const double stage = (u_per_tile + v_per_tile) * mg_repeat / 48.0;
       double cost = (mgen + stage + extra_mfma(tg) + 24.0) / real;
-      if (bytes > 80 * 1024) cost *= 1.15;   // one workgroup per CU
+      // above 80 KB only one workgroup fits a CU, and none overlaps its
+      // staging with another's MFMA work (measured: 1.3x-1.5x slower)
+      if (bytes > 80 * 1024) cost *= 1.5;
       const double par = (double)tg.nColTiles * mg_repeat;
       if (par < 512.0) cost *= 512.0 / std::max(par, 1.0);   // too few tiles to fill 256 CUs
       if (cost < best_cost * 0.999) {
@@ -375,7 +377,9 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
   r.Ik = g.Ik;
   r.ip = g.ip;
   const int lda = ld_mod(r.sp, 16);
-  const bool stage_a = (size_t)r.ip * lda * es <= 64 * 1024;
+  // A_k(k) in LDS only when small: a large copy would leave room for one
+  // workgroup per CU (it is read through the cache otherwise)
+  const bool stage_a = (size_t)r.ip * lda * es <= 24 * 1024;
   r.lda = stage_a ? lda : 0;
   auto rec_lds = [&](const TileGeom& tg) {
     const int ldm = ld_mod(std::max(r.sp, 4), 4);
@@ -389,7 +393,8 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
   r.tg.tcolp = pad16(r.tg.tcol);
   r.ldm = ld_mod(std::max(r.sp, 4), 4);
   r.lds_bytes = rec_lds(r.tg);
-  r.nblk = (int32_t)std::min<int64_t>(r.tg.nColTiles, 2048);
+  // two workgroups per CU, each walking a contiguous range of column tiles
+  r.nblk = (int32_t)std::min<int64_t>(r.tg.nColTiles, 512);
   return r.lds_bytes <= (size_t)gram_max_lds_bytes();
 }
 

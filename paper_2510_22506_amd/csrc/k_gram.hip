@@ -14,6 +14,13 @@
 
 namespace fctn {
 
+// Phase hooks for timing probes (empty in the library).
+#ifndef FCTN_GRAM_MARK
+#define FCTN_GRAM_MARK_INIT
+#define FCTN_GRAM_MARK(n)
+#define FCTN_GRAM_MARK_FLUSH
+#endif
+
 constexpr int kGramThreads = 512;   // 8 waves
 constexpr int kGramWaves = kGramThreads / 64;
 constexpr int kTPW = 16;            // output tiles per wave
@@ -155,8 +162,10 @@ __device__ inline void stage_operands(const MGen& mg, const TileGeom& tg, const 
   }
 }
 
+// float32: at most 128 VGPRs, so that two workgroups share a CU and one
+// stages its next tile while the other runs MFMA (float64 keeps one per CU)
 template <typename T>
-__global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __restrict__ X,
+__global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MGen mg, const T* __restrict__ X,
                                                            XView xv, GramGeom g,
                                                            T* __restrict__ part) {
   typedef Mfma<T> MM;
@@ -172,7 +181,10 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
   const T* U = (const T*)mg.U;
   const T* V = (const T*)mg.V;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index as a wave-uniform (scalar) value, so that tile-selection
+  // branches are scalar branches rather than per-lane masks
+  const int tid = threadIdx.x, lane = tid & 63,
+            wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int split = blockIdx.x, group = blockIdx.y;
   const int t0 = group * g.tilesPerGroup;
   const int t1 = min(t0 + g.tilesPerGroup, g.nTiles);
@@ -225,10 +237,12 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
   const bool x_rfast = xv.x_ik == 1;
   const int xl = x_rfast ? min(xrows, 16) : 16;   // xrows is a multiple of 16
 
+  FCTN_GRAM_MARK_INIT
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
     stage_operands<T>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
                       kGramThreads);
+    FCTN_GRAM_MARK(0);
     if (xrows > 0) {
       const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
       const int64_t lim_u = mg.Cu - cu0, lim_v = mg.Cv - cv0;
@@ -251,9 +265,13 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
         }
       }
     }
+    FCTN_GRAM_MARK(1);
     __syncthreads();
+    FCTN_GRAM_MARK(2);
     mgen_mfma<T>(tg, Us, Vs, ptab, qtab, Ms, lane, wave, kGramWaves);
+    FCTN_GRAM_MARK(3);
     __syncthreads();
+    FCTN_GRAM_MARK(4);
     const int kr = lane >> 4;
 #pragma unroll
     for (int j = 0; j < kTPW; ++j) {
@@ -267,8 +285,11 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_k(MGen mg, const T* __r
         }
       }
     }
+    FCTN_GRAM_MARK(5);
     __syncthreads();
+    FCTN_GRAM_MARK(6);
   }
+  FCTN_GRAM_MARK_FLUSH
 
 #pragma unroll
   for (int j = 0; j < kTPW; ++j) {
@@ -293,8 +314,11 @@ int gram_tiles_per_group() { return kGramWaves * kTPW; }
 // 16-byte load.  With X3 each value is also kept as a bf16 residual
 // (x = hi + lo) and every product is hi*hi + hi*lo + lo*hi.
 // ---------------------------------------------------------------------------
+// bf16: at most 128 VGPRs (two workgroups per CU, as for float32); the split
+// form keeps the default budget (its tiles need more than half a CU's LDS,
+// so it runs one workgroup per CU anyway)
 template <int X3>
-__global__ void __launch_bounds__(kGramThreads) gram_rhs_bf16_k(MGen mg, const float* __restrict__ X,
+__global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen mg, const float* __restrict__ X,
                                                                 XView xv, GramGeom g,
                                                                 float* __restrict__ part) {
   typedef Mfma<float> MF;
@@ -313,7 +337,10 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_bf16_k(MGen mg, const f
   const float* U = (const float*)mg.U;
   const float* V = (const float*)mg.V;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index as a wave-uniform (scalar) value, so that tile-selection
+  // branches are scalar branches rather than per-lane masks
+  const int tid = threadIdx.x, lane = tid & 63,
+            wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int split = blockIdx.x, group = blockIdx.y;
   const int t0 = group * g.tilesPerGroup;
   const int t1 = min(t0 + g.tilesPerGroup, g.nTiles);
@@ -324,8 +351,11 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_bf16_k(MGen mg, const f
     ba_lo = bfirst;
     xrows = (blast - bfirst + 1) * 16;
   }
-  int arow[kTPW], brow[kTPW];
-  bool fromX[kTPW], valid[kTPW];
+  // this wave's output tiles (wave-uniform): bit 0 = A operand from X_(k),
+  // bits 1-10 = row block bi, bits 11-20 = column block bj; the lane's own
+  // offset inside a 16-row block is loff
+  int tdesc[kTPW];
+  bool valid[kTPW];
   MF::acc_t acc[kTPW];
 #pragma unroll
   for (int j = 0; j < kTPW; ++j) {
@@ -333,7 +363,7 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_bf16_k(MGen mg, const f
     valid[j] = t < t1;
     acc[j] = MF::zero();
     int bi = 0, bj = 0;
-    fromX[j] = false;
+    bool fromX = false;
     if (valid[j]) {
       if (t < g.nG) {
         upper_tile(t, bi, bj);
@@ -341,12 +371,12 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_bf16_k(MGen mg, const f
         const int tb = t - g.nG;
         bi = tb / g.nbj - ba_lo;
         bj = tb % g.nbj;
-        fromX[j] = true;
+        fromX = true;
       }
     }
-    arow[j] = (bi * 16 + (lane & 15)) * ldb + 8 * (lane >> 4);
-    brow[j] = (bj * 16 + (lane & 15)) * ldb + 8 * (lane >> 4);
+    tdesc[j] = (fromX ? 1 : 0) | (bi << 1) | (bj << 11);
   }
+  const int loff = (lane & 15) * ldb + 8 * (lane >> 4);
 
   build_tables(mg, tg, &xv, ldb, 1, ptab, qtab, ctab, tid, kGramThreads);
   {
@@ -395,18 +425,23 @@ __global__ void __launch_bounds__(kGramThreads) gram_rhs_bf16_k(MGen mg, const f
 #pragma unroll
       for (int j = 0; j < kTPW; ++j) {
         if (valid[j]) {
-          const uint16_t* Ah = fromX[j] ? Xh : Mh;
-          const bf16x8 a = *(const bf16x8*)(Ah + arow[j] + kk);
-          const bf16x8 b = *(const bf16x8*)(Mh + brow[j] + kk);
+          const int d = tdesc[j];
+          const int ao = ((d >> 1) & 1023) * 16 * ldb + loff + kk;
+          const int bo = (d >> 11) * 16 * ldb + loff + kk;
+          const uint16_t* Ah = (d & 1) ? Xh : Mh;
+          const bf16x8 a = *(const bf16x8*)(Ah + ao);
+          const bf16x8 b = *(const bf16x8*)(Mh + bo);
           acc[j] = MfmaBf16::mma(a, b, acc[j]);
           if (X3) {
-            const uint16_t* Al = fromX[j] ? Xl : Ml;
-            const bf16x8 al = *(const bf16x8*)(Al + arow[j] + kk);
-            const bf16x8 bl = *(const bf16x8*)(Ml + brow[j] + kk);
+            const uint16_t* Al = (d & 1) ? Xl : Ml;
+            const bf16x8 al = *(const bf16x8*)(Al + ao);
+            const bf16x8 bl = *(const bf16x8*)(Ml + bo);
             acc[j] = MfmaBf16::mma(a, bl, acc[j]);
             acc[j] = MfmaBf16::mma(al, b, acc[j]);
           }
         }
+        // at most two tiles' fragments in flight (register budget)
+        if (j & 1) __builtin_amdgcn_sched_barrier(0);
       }
     }
     __syncthreads();
@@ -513,13 +548,19 @@ hipError_t launch_reduce_gb(int prec, const GramGeom& g, const void* part, const
 // ---------------------------------------------------------------------------
 // Z_(k) = A_k(k) M_k: per column tile the block of M_k is generated on MFMA
 // into LDS (the same generator as above), then Z's 16x16 tiles
-// (i_k block x column block) accumulate on MFMA over the s_k rows.  A_k(k) is
-// staged in LDS when it fits.  Each workgroup walks a contiguous range of
-// column tiles so that operand slabs are reused.  Z is written through the X view.
+// (i_k block x column block) accumulate on MFMA over the s_k rows; a wave
+// takes one i_k block and two column blocks, so that one A fragment feeds two
+// independent MFMAs.  A_k(k) is staged in LDS when it is small, else read
+// through the cache.  Each workgroup walks a contiguous range of column tiles
+// so that operand slabs are reused.  Z is written through the X view.
 // ---------------------------------------------------------------------------
+constexpr int kRecThreads = 512;
+constexpr int kRecWaves = kRecThreads / 64;
+
 template <typename T>
-__global__ void __launch_bounds__(256) reconstruct_k(MGen mg, const T* __restrict__ Au,
-                                                     T* __restrict__ Z, XView xv, RecGeom g) {
+__global__ void __launch_bounds__(kRecThreads) reconstruct_k(MGen mg, const T* __restrict__ Au,
+                                                             T* __restrict__ Z, XView xv,
+                                                             RecGeom g) {
   typedef Mfma<T> MM;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileGeom& tg = g.tg;
@@ -531,52 +572,84 @@ __global__ void __launch_bounds__(256) reconstruct_k(MGen mg, const T* __restric
   T* As = Ms + (int64_t)tg.tcolp * g.ldm;     // [ip][lda] when staged
   const T* U = (const T*)mg.U;
   const T* V = (const T*)mg.V;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index as a wave-uniform (scalar) value
+  const int tid = threadIdx.x, lane = tid & 63,
+            wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int kr = lane >> 4, lc = lane & 15;
 
-  build_tables(mg, tg, nullptr, 1, g.ldm, ptab, qtab, nullptr, tid, 256);
-  for (int e = tid; e < tg.tcolp * g.ldm; e += 256) Ms[e] = T(0);
+  build_tables(mg, tg, nullptr, 1, g.ldm, ptab, qtab, nullptr, tid, kRecThreads);
+  for (int e = tid; e < tg.tcolp * g.ldm; e += kRecThreads) Ms[e] = T(0);
   if (g.lda > 0) {
-    for (int e = tid; e < g.ip * g.sp; e += 256) {
+    for (int e = tid; e < g.ip * g.sp; e += kRecThreads) {
       const int i = e / g.sp, r = e - (e / g.sp) * g.sp;
       As[i * g.lda + r] = (i < g.Ik && r < g.s) ? Au[(int64_t)i * g.s + r] : T(0);
     }
   }
   __syncthreads();
 
-  const int nib = g.ip / 16, ncb = tg.tcolp / 16;
+  const int nib = g.ip / 16, ncb = tg.tcolp / 16, ncg = (ncb + 1) / 2;
   const int64_t per = (tg.nColTiles + gridDim.x - 1) / gridDim.x;
   const int64_t ct0 = (int64_t)blockIdx.x * per, ct1 = min(ct0 + per, tg.nColTiles);
   int64_t cur_tu = -1, cur_tv = -1;
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
     const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
-    stage_operands<T>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid, 256);
+    stage_operands<T>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
+                      kRecThreads);
     __syncthreads();
-    mgen_mfma<T>(tg, Us, Vs, ptab, qtab, Ms, lane, wave, 4);
+    mgen_mfma<T>(tg, Us, Vs, ptab, qtab, Ms, lane, wave, kRecWaves);
     __syncthreads();
-    for (int t = wave; t < nib * ncb; t += 4) {
-      const int ib = t / ncb, cb = t - (t / ncb) * ncb;
-      typename MM::acc_t acc = MM::zero();
+    for (int it = wave; it < nib * ncg; it += kRecWaves) {
+      const int ib = it / ncg, cb0 = 2 * (it - (it / ncg) * ncg);
+      const bool two = cb0 + 1 < ncb;
+      typename MM::acc_t acc0 = MM::zero(), acc1 = MM::zero();
       const int ik_a = ib * 16 + lc;
-      for (int k0 = 0; k0 < g.sp; k0 += MM::kStep) {
-        const int row = k0 + kr;
-        T a;
-        if (g.lda > 0) a = As[ik_a * g.lda + row];
-        else a = (ik_a < g.Ik && row < g.s) ? Au[(int64_t)ik_a * g.s + row] : T(0);
-        const T b = Ms[(cb * 16 + lc) * g.ldm + row];
-        acc = MM::mma(a, b, acc);
+      const bool oka = ik_a < g.Ik;
+      const int ika = oka ? ik_a : 0;
+      const T* m0 = Ms + (cb0 * 16 + lc) * g.ldm;
+      const T* m1 = m0 + 16 * g.ldm;
+      if (two) {
+#pragma unroll 4
+        for (int k0 = 0; k0 < g.sp; k0 += MM::kStep) {
+          const int row = k0 + kr;
+          T a;
+          if (g.lda > 0) {
+            a = As[ik_a * g.lda + row];
+          } else {
+            const T av = Au[(int64_t)ika * g.s + min(row, g.s - 1)];
+            a = (oka && row < g.s) ? av : T(0);
+          }
+          acc0 = MM::mma(a, m0[row], acc0);
+          acc1 = MM::mma(a, m1[row], acc1);
+        }
+      } else {
+#pragma unroll 4
+        for (int k0 = 0; k0 < g.sp; k0 += MM::kStep) {
+          const int row = k0 + kr;
+          T a;
+          if (g.lda > 0) {
+            a = As[ik_a * g.lda + row];
+          } else {
+            const T av = Au[(int64_t)ika * g.s + min(row, g.s - 1)];
+            a = (oka && row < g.s) ? av : T(0);
+          }
+          acc0 = MM::mma(a, m0[row], acc0);
+        }
       }
-      const int c = cb * 16 + lc;
-      if (c < tg.tcol) {
-        const int cul = c / tg.TCv, cvl = c - (c / tg.TCv) * tg.TCv;
-        const int64_t cu = cu0 + cul, cv = cv0 + cvl;
-        if (cu < mg.Cu && cv < mg.Cv) {
-          const int64_t base = cu * xv.x_cu + cv * xv.x_cv;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int ik = ib * 16 + MM::row(lane, i);
-            if (ik < xv.Ik) Z[base + (int64_t)ik * xv.x_ik] = acc[i];
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && !two) break;
+        const int c = (cb0 + h) * 16 + lc;
+        if (c < tg.tcol) {
+          const int cul = c / tg.TCv, cvl = c - (c / tg.TCv) * tg.TCv;
+          const int64_t cu = cu0 + cul, cv = cv0 + cvl;
+          if (cu < mg.Cu && cv < mg.Cv) {
+            const int64_t base = cu * xv.x_cu + cv * xv.x_cv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int ik = ib * 16 + MM::row(lane, i);
+              if (ik < xv.Ik) Z[base + (int64_t)ik * xv.x_ik] = h ? acc1[i] : acc0[i];
+            }
           }
         }
       }
@@ -590,13 +663,13 @@ hipError_t launch_reconstruct(int prec, const MGen& mg, const void* Au, void* Z,
   if (prec == P_F64) {
     hipFuncSetAttribute((const void*)reconstruct_k<double>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    reconstruct_k<double><<<g.nblk, 256, g.lds_bytes, st>>>(mg, (const double*)Au, (double*)Z,
-                                                            xv, g);
+    reconstruct_k<double><<<g.nblk, kRecThreads, g.lds_bytes, st>>>(mg, (const double*)Au,
+                                                                    (double*)Z, xv, g);
   } else {
     hipFuncSetAttribute((const void*)reconstruct_k<float>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    reconstruct_k<float><<<g.nblk, 256, g.lds_bytes, st>>>(mg, (const float*)Au, (float*)Z, xv,
-                                                           g);
+    reconstruct_k<float><<<g.nblk, kRecThreads, g.lds_bytes, st>>>(mg, (const float*)Au,
+                                                                   (float*)Z, xv, g);
   }
   return hipGetLastError();
 }
