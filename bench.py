@@ -167,6 +167,32 @@ def serving(args):
     return out
 
 
+def xpass_large(dims=(1024, 1024, 256), launches=10):
+    """The X/mask pass (eq. 10, x_update_k) on a float32 tensor of 1 GiB per
+    operand, larger than the 256 MB Infinity Cache, so that its rate is HBM's:
+    reads X, Z and the mask bits, writes X (12.125 bytes per element)."""
+    import torch
+    from paper_2510_22506_amd import Plan
+    plan = Plan(dims, (2, 2, 2), precision="f32")
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(7)
+    Y = torch.rand(dims, device="cuda:0", generator=g)
+    mask = (torch.rand(dims, device="cuda:0", generator=g) < 0.05).to(torch.uint8)
+    Z = torch.rand(dims, device="cuda:0", generator=g)
+    plan.set_observed(Y, mask)
+    del Y, mask
+    plan.step_x_update(Z)
+    plan.profile_enable(True)
+    plan.profile_read(reset=True)
+    for _ in range(launches):
+        plan.step_x_update(Z)
+    rec = plan.profile_read(reset=True)["x_update"]
+    plan.close()
+    r = stage_roofline("x_update", rec, "f32")
+    r.update({"dims": list(dims), "bytes_per_launch": rec["bytes"] / max(rec["launches"], 1)})
+    return r
+
+
 def cpu_baseline(prob, sweeps):
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -198,6 +224,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="add the per-stage breakdown")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-xpass-large", action="store_true",
+                    help="skip the X/mask pass on a 1 GiB tensor")
     ap.add_argument("--serve-n", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-sweeps", type=int, default=30)
@@ -284,6 +312,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         line["calibration_copy_bytes"] = src.numel() * 4
+    if not args.no_xpass_large:
+        try:
+            line["roofline_xpass_large"] = xpass_large()
+        except Exception as e:  # reported, never hides the sweep measurement
+            line["roofline_xpass_large"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_serve:
         try:
             line["serving"] = serving(args)

@@ -22,7 +22,6 @@ using namespace fctn;
 namespace {
 
 constexpr int kHist = 4096;
-constexpr int kXBlocks = 1024;
 constexpr int kTargetGramWGs = 512;
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -97,6 +96,7 @@ struct fctn_plan_s {
   double* lam_half;
   int32_t* ncls_dev;
   double* xpart;
+  int xblocks;      // blocks of the X update (one partial triple each)
   double* hist;
   double* scratch_slot;
   ModeInfo mode[4];
@@ -434,7 +434,8 @@ size_t carve(fctn_plan_s* P, char* base) {
   P->trace_part = (double*)c.take((size_t)N * P->max_cls * sizeof(double));
   P->lam_half = (double*)c.take(N * sizeof(double));
   P->ncls_dev = (int32_t*)c.take(N * sizeof(int32_t));
-  P->xpart = (double*)c.take(kXBlocks * 3 * sizeof(double));
+  P->xblocks = x_update_blocks(P->prec, P->numel);
+  P->xpart = (double*)c.take((size_t)P->xblocks * 3 * sizeof(double));
   P->hist = (double*)c.take(kHist * 4 * sizeof(double));
   P->scratch_slot = (double*)c.take(4 * sizeof(double));
   return align256(c.off);
@@ -615,10 +616,10 @@ fctn_status reconstruct(fctn_plan_s* P, int k, void* Z) {
 fctn_status x_update(fctn_plan_s* P, const void* Z, double* slot, bool with_trace) {
   FCTN_TIMED(P, FCTN_STAGE_XUPDATE, 5.0 * P->numel,
              3.0 * P->numel * P->es + P->numel / 8.0,
-             launch_x_update(P->prec, P->X, Z, P->bits, P->d.rho, P->numel, kXBlocks, P->xpart,
+             launch_x_update(P->prec, P->X, Z, P->bits, P->d.rho, P->numel, P->xblocks, P->xpart,
                              P->st));
-  FCTN_TIMED(P, FCTN_STAGE_STATS, 3.0 * kXBlocks, 24.0 * kXBlocks,
-             launch_stats(P->xpart, kXBlocks, P->trace_part, P->lam_half, P->ncls_dev,
+  FCTN_TIMED(P, FCTN_STAGE_STATS, 3.0 * P->xblocks, 24.0 * P->xblocks,
+             launch_stats(P->xpart, P->xblocks, P->trace_part, P->lam_half, P->ncls_dev,
                           with_trace ? P->N : 0, P->max_cls, slot, P->st));
   return FCTN_OK;
 }

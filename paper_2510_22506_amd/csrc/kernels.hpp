@@ -117,6 +117,8 @@ hipError_t launch_backtransform(int prec, const double* Q, const double* At, int
                                 hipStream_t st);
 hipError_t launch_reconstruct(int prec, const MGen& mg, const void* Au, void* Z,
                               const XView& xv, const RecGeom& g, hipStream_t st);
+// blocks of x_update_k for n elements (one 16-byte vector per thread)
+int x_update_blocks(int prec, int64_t n);
 hipError_t launch_x_update(int prec, void* X, const void* Z, const uint32_t* bits, double rho,
                            int64_t n, int nblk, double* xpart, hipStream_t st);
 hipError_t launch_stats(const double* xpart, int nblk, const double* trace_part,
