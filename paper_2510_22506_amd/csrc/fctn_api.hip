@@ -463,6 +463,8 @@ bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
   if (P->numel >= ((int64_t)1 << 31)) return false;
   for (int p = 0; p < 2; ++p)
     if (P->pnum[p] >= ((int64_t)1 << 31)) return false;
+  for (int k = 0; k < P->N; ++k)
+    if (P->fnum[k] >= ((int64_t)1 << 31)) return false;
   for (int k = 0; k < P->N; ++k) {
     if (!solve_supported((int32_t)P->mode[k].s)) return false;
     if (!setup_geom(P->mode[k], P->es, P->prec)) return false;

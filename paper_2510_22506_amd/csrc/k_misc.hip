@@ -158,30 +158,37 @@ hipError_t launch_build_basis(double* Q, double* Qt, double* lam_col, int32_t n,
 // Pair tensor of the reuse mechanism (two factors contracted over their
 // shared bond), written in the layout the sub-network generator reads.
 // ---------------------------------------------------------------------------
+// One output per thread, so that a wave's stores are contiguous; the pair
+// tensor and the factors stay below 2^31 elements (checked on the host), so
+// every index is 32-bit (64-bit division would dominate the kernel).
 template <typename T>
 __global__ void __launch_bounds__(256) pair_k(PairDesc pd, T* __restrict__ P, int64_t total) {
   const T* Fa = (const T*)pd.Fa;
   const T* Fb = (const T*)pd.Fb;
-  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
-       o += (int64_t)gridDim.x * blockDim.x) {
-    int64_t q = o;
-    const int b2 = (int)(q % pd.n2b); q /= pd.n2b;
-    const int a2 = (int)(q % pd.n2a); q /= pd.n2a;
-    const int b1 = (int)(q % pd.n1b); q /= pd.n1b;
-    const int a1 = (int)(q % pd.n1a); q /= pd.n1a;
-    const int ib = (int)(q % pd.Ib);
-    const int ia = (int)(q / pd.Ib);
-    const T* pa = Fa + ia * pd.a_i + a1 * pd.a_1 + a2 * pd.a_2;
-    const T* pb = Fb + ib * pd.b_i + b1 * pd.b_1 + b2 * pd.b_2;
+  const uint32_t n = (uint32_t)total;
+  const uint32_t n2b = pd.n2b, n2a = pd.n2a, n1b = pd.n1b, n1a = pd.n1a, Ib = pd.Ib;
+  const int a_i = (int)pd.a_i, a_1 = (int)pd.a_1, a_2 = (int)pd.a_2, a_k = (int)pd.a_k;
+  const int b_i = (int)pd.b_i, b_1 = (int)pd.b_1, b_2 = (int)pd.b_2, b_k = (int)pd.b_k;
+  for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < n; o += gridDim.x * blockDim.x) {
+    uint32_t q = o;
+    const uint32_t b2 = q % n2b; q /= n2b;
+    const uint32_t a2 = q % n2a; q /= n2a;
+    const uint32_t b1 = q % n1b; q /= n1b;
+    const uint32_t a1 = q % n1a; q /= n1a;
+    const uint32_t ib = q % Ib, ia = q / Ib;
+    const T* pa = Fa + (int)ia * a_i + (int)a1 * a_1 + (int)a2 * a_2;
+    const T* pb = Fb + (int)ib * b_i + (int)b1 * b_1 + (int)b2 * b_2;
     T acc = T(0);
-    for (int k = 0; k < pd.K; ++k) acc += pa[k * pd.a_k] * pb[k * pd.b_k];
+#pragma unroll 4
+    for (int k = 0; k < pd.K; ++k) acc += pa[k * a_k] * pb[k * b_k];
     P[o] = acc;
   }
 }
 
 hipError_t launch_pair(int prec, const PairDesc& pd, void* P, hipStream_t st) {
   const int64_t total = (int64_t)pd.Ia * pd.Ib * pd.n1a * pd.n1b * pd.n2a * pd.n2b;
-  const int nb = (int)(cdiv(total, 256) < 4096 ? cdiv(total, 256) : 4096);
+  const int nb = (int)(cdiv(total, 256) < 8192 ? cdiv(total, 256) : 8192);
+  if (total == 0) return hipSuccess;
   if (prec == P_F64)
     pair_k<double><<<nb, 256, 0, st>>>(pd, (double*)P, total);
   else
