@@ -1,0 +1,50 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (reuse on, alternating order): two PAM sweeps of the image-shaped
+256x256x3, video-shaped 144x176x3x50 and multispectral-shaped 512x512x31
+configurations against the FP64 oracle on the same seeded inputs (the oracle
+finishes a sweep of each in a few seconds).  float32 to 1e-5 relative, split
+bf16 to 2e-4, observed entries bit for bit, and the per-sweep objective and
+relative change to the same tolerance."""
+
+import numpy as np
+import pytest
+
+from oracle import pam
+from workloads import make_problem
+
+pytestmark = pytest.mark.gpu
+
+SWEEPS = 2
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("name,prec,tol", [
+    ("c2", "f32", 1e-5), ("c3", "f32", 1e-5), ("c4", "f32", 1e-5),
+    ("c3", "bf16x3", 2e-4), ("c4", "bf16x3", 2e-4),
+])
+def test_full_size_sweeps(name, prec, tol):
+    from paper_2510_22506_amd import Plan
+    prob = make_problem(name, seed=0, precision="f32")
+    p = Plan(prob.dims, prob.ranks, prob.lam, prob.delta, prob.rho, precision=prec,
+             reuse=True, order_policy=1)
+    p.set_factors(prob.A0)
+    p.set_observed(prob.Y, prob.mask)
+    p.sweep(SWEEPS)
+    hist = p.history(0, SWEEPS)
+    Xg = p.x().cpu().numpy()
+    p.close()
+    A0 = [a.astype(np.float32).astype(np.float64) for a in prob.A0]
+    Xo, _, st = pam.complete(prob.Y.astype(np.float64), prob.mask != 0, prob.ranks, prob.lam,
+                             prob.delta, prob.rho, SWEEPS, A0, reuse=True, order_policy=1)
+    print(f"{name} {prob.dims} {prec}: rel err {_rel(Xg, Xo):.3e}")
+    assert _rel(Xg, Xo) <= tol, _rel(Xg, Xo)
+    obs = prob.mask != 0
+    np.testing.assert_array_equal(Xg[obs], prob.Y[obs])
+    for t in range(SWEEPS):
+        assert abs(hist[t]["objective"] - st["objective"][t]) <= 10 * tol * abs(st["objective"][t])
+        assert abs(hist[t]["rel_change"] - st["rel_change"][t]) <= 10 * tol * st["rel_change"][t]
