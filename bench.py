@@ -39,8 +39,10 @@ WORKLOADS = {
     "c2": ("c2", None, "color-image order-3 256x256x3, ranks (12,3,3), SR 0.1"),
     "c4": ("c4", None, "multispectral order-3 512x512x31, ranks (16,8,8), SR 0.05"),
     "c1": ("c1", None, "low-rank order-3 32x32x8, ranks (3,3,3), SR 0.3"),
+    "c5": ("c5", None, "new-video-shaped order-4 500x550x3x24, ranks (8,3,8,3,8,3), SR 0.05"),
+    "c6": ("c6", None, "multi-temporal order-4 300x300x4x5, ranks (8,3,4,3,4,3), SR 0.05"),
 }
-DEFAULT_PREC = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f32"}
+DEFAULT_PREC = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f32", "c5": "f32", "c6": "f32"}
 # contraction stages: their algorithmic flops make up tflops_contractions;
 # gram_rhs and reconstruct run on MFMA, pair on the vector ALUs writing the
 # pair tensor (HBM-bound)

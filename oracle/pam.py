@@ -28,6 +28,16 @@ sweep is still current for the first two updates of the next.  With reuse on
 this gives exactly Table 1's counts (t = 1: 4I^2R^5 + 8I^3R^5; t >= 2:
 2I^2R^5 + 8I^3R^5; X: 2I^4R^3).  For N != 4 policy 1 equals policy 0.
 
+Asymmetric extrapolation (Section 4.2, used there for the multi-temporal
+images; off unless `extrapolation=(alpha, beta)` is given): right after factor
+k's subproblem is solved, the new factor A is replaced by
+A + alpha (A - beta A^t), with A^t the factor the subproblem started from (its
+proximal centre).  The paper states the update but not where it sits in the
+loop; it is read here as part of each factor's block, so the factors updated
+later in the sweep, FCTN(A^{t+1}) in the X step and the next sweep's proximal
+centre all see the extrapolated factor.  The PAM objective is then no longer
+monotone.
+
 Initial X is P_Omega(Y): the observed tensor is zero off Omega by definition
 of a partial observation (Section 1), so Algorithm 1's X^(1) = Y is read as
 P_Omega(Y); values of Y off Omega never enter any arithmetic.
@@ -153,7 +163,7 @@ def x_update(X, Z, mask, rho):
 
 
 def complete(Y, mask, ranks, lam, delta, rho, sweeps, A0, tol=0.0, reuse=True,
-             order_policy=0, record_blocks=False, counters=None):
+             order_policy=0, record_blocks=False, counters=None, extrapolation=None):
     """Run PAM (Algorithm 1 if reuse is False, Algorithm 2 if True).
 
     Y, mask: observed tensor and boolean Omega of shape I_1 x .. x I_N.
@@ -162,6 +172,7 @@ def complete(Y, mask, ranks, lam, delta, rho, sweeps, A0, tol=0.0, reuse=True,
     Returns (X, factors, stats) where stats holds per-sweep rel_change,
     objective and, with record_blocks, the objective after every block.
     counters: optional list that receives one FlopCounter per sweep.
+    extrapolation: None, or (alpha, beta) of the asymmetric extrapolation.
     """
     Y = np.asarray(Y, dtype=np.float64)
     mask = np.asarray(mask, dtype=bool)
@@ -189,6 +200,9 @@ def complete(Y, mask, ranks, lam, delta, rho, sweeps, A0, tol=0.0, reuse=True,
             Yk = sylvester.rhs(Xk, Mk, Ak, rho)
             counter.add("rhs", 2 * Xk.shape[0] * Mk.shape[0] * Mk.shape[1])
             Anew = sylvester.solve_fast(G, Yk, lam[k], delta[k], rho)
+            if extrapolation is not None:
+                alpha, beta = extrapolation
+                Anew = Anew + alpha * (Anew - beta * Ak)
             factors[k] = tensor.fold(Anew, k, shapes[k])
             versions[k] += 1
             if record_blocks:

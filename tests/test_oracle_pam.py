@@ -196,6 +196,13 @@ def test_generators_shapes_and_ranges():
     assert q.Y.dtype == np.float32 and q.Y.shape == (24, 28, 3, 6)
     r = make_problem("c4", seed=2, dims=(40, 36, 31))
     assert r.truth.min() == 0.0 and r.truth.max() == 1.0
+    m = make_problem("c6", seed=3, dims=(30, 28, 4, 5))
+    assert m.Y.shape == (30, 28, 4, 5) and m.truth.min() == 0.0 and m.truth.max() == 1.0
+    assert [a.shape for a in m.A0] == factor_shapes_of(m.dims, m.ranks)
+    # dates differ (blobs drift and change amplitude between acquisitions)
+    assert np.abs(m.truth[..., 0] - m.truth[..., 4]).max() > 1e-3
+    v = make_problem("c5", seed=4, dims=(20, 22, 3, 4))
+    assert v.Y.shape == (20, 22, 3, 4) and abs(v.mask.mean() - 0.05) < 0.03
 
 
 def test_c1_quality_improves():
@@ -204,3 +211,54 @@ def test_c1_quality_improves():
     X, _, st = pam.complete(p.Y, p.mask != 0, p.ranks, p.lam, p.delta, p.rho, p.sweeps, p.A0)
     assert metrics.psnr(p.truth, X) > metrics.psnr(p.truth, p.Y) + 5.0
     assert all(b <= a * (1 + 1e-12) for a, b in zip(st["objective"], st["objective"][1:]))
+
+
+# --- asymmetric extrapolation (Section 4.2) --------------------------------
+
+def _small(seed=5, dims=(6, 5, 4), ranks=(2, 3, 2)):
+    rng = np.random.default_rng(seed)
+    Y = rng.random(dims)
+    mask = rng.random(dims) < 0.4
+    A0 = init_factors(rng, dims, ranks)
+    return Y, mask, ranks, A0
+
+
+def test_extrapolation_alpha_zero_is_plain():
+    Y, mask, ranks, A0 = _small()
+    X0, F0, s0 = pam.complete(Y, mask, ranks, 0.3, 0.5, 0.1, 3, A0)
+    X1, F1, s1 = pam.complete(Y, mask, ranks, 0.3, 0.5, 0.1, 3, A0, extrapolation=(0.0, 0.7))
+    # equal up to the summation order of BLAS on a differently strided copy
+    np.testing.assert_allclose(X1, X0, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(s1["objective"], s0["objective"], rtol=1e-12)
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.5, 0.5), (0.3, 0.6), (0.4, 1.0), (0.7, 0.0)])
+def test_extrapolation_proximal_limit(alpha, beta):
+    # rho -> infinity pins every subproblem to its proximal centre
+    # (A_new = A^t + O(1/rho)), so after one sweep each factor is
+    # (1 + alpha - alpha beta) times its initial value; beta = 1 leaves it
+    # unchanged and beta = 0 scales it by 1 + alpha.
+    Y, mask, ranks, A0 = _small()
+    rho = 1e10
+    _, F, _ = pam.complete(Y, mask, ranks, 0.3, 0.5, rho, 1, A0,
+                           extrapolation=(alpha, beta))
+    c = 1.0 + alpha - alpha * beta
+    for a, a0 in zip(F, A0):
+        np.testing.assert_allclose(a, c * a0, rtol=1e-6, atol=1e-8)
+
+
+def test_extrapolation_first_order_weight():
+    # to first order in 1/rho the plain update moves the first factor by D/rho;
+    # the extrapolated factor is c A^t plus (1 + alpha) times that move (the
+    # extrapolation acts on the new factor, not on the proximal centre, which
+    # would give alpha times the move)
+    Y, mask, ranks, A0 = _small(seed=8)
+    rho, alpha, beta = 1e6, 0.5, 0.5
+    _, Fp, _ = pam.complete(Y, mask, ranks, 0.3, 0.5, rho, 1, A0)
+    _, Fe, _ = pam.complete(Y, mask, ranks, 0.3, 0.5, rho, 1, A0,
+                            extrapolation=(alpha, beta))
+    move = Fp[0] - A0[0]
+    extra = Fe[0] - (1.0 + alpha - alpha * beta) * A0[0]
+    assert np.abs(move).max() > 1e-7
+    np.testing.assert_allclose(extra, (1.0 + alpha) * move, rtol=1e-4,
+                               atol=1e-4 * np.abs(move).max())

@@ -158,6 +158,36 @@ def multispectral(rng, H, W, B=31, n_end=8, n_peaks=4):
     return (cube - cube.min()) / (cube.max() - cube.min())
 
 
+def multitemporal(rng, H, W, B=4, T=5, n_end=6, n_peaks=3):
+    """H x W x B x T multi-temporal cube (height, width, band, time): n_end
+    endmembers, each a spectrum of n_peaks Gaussian peaks sampled at B band
+    centres spread over 450-850 nm (peak centre U(450, 850), width U(40, 150)
+    nm, amplitude U(0.2, 1)) times a Gaussian-blob abundance map (centre
+    U(0.1, 0.9), sigma U(0.05, 0.3) of the side); between acquisitions each
+    blob centre drifts by U(-0.02, 0.02) of the side and its amplitude follows
+    1 + 0.3 sin(2 pi t / T + phase), phase U(0, 2 pi); min-max to [0, 1]."""
+    y, x = np.meshgrid(np.arange(H) / H, np.arange(W) / W, indexing="ij")
+    lam = np.linspace(450.0, 850.0, B)
+    cube = np.zeros((H, W, B, T))
+    for _ in range(n_end):
+        cy, cx = rng.uniform(0.1, 0.9, size=2)
+        sg = rng.uniform(0.05, 0.3)
+        phase = rng.uniform(0.0, 2.0 * np.pi)
+        spec = np.zeros(B)
+        for _ in range(n_peaks):
+            c = rng.uniform(450.0, 850.0)
+            w = rng.uniform(40.0, 150.0)
+            a = rng.uniform(0.2, 1.0)
+            spec += a * np.exp(-((lam - c) ** 2) / (2 * w * w))
+        for t in range(T):
+            if t > 0:
+                cy, cx = np.array([cy, cx]) + rng.uniform(-0.02, 0.02, size=2)
+            amp = 1.0 + 0.3 * np.sin(2.0 * np.pi * t / T + phase)
+            ab = amp * np.exp(-((y - cy) ** 2 + (x - cx) ** 2) / (2 * sg * sg))
+            cube[:, :, :, t] += ab[:, :, None] * spec[None, None, :]
+    return (cube - cube.min()) / (cube.max() - cube.min())
+
+
 # ----------------------------------------------------------------------------
 # problem configurations
 # ----------------------------------------------------------------------------
@@ -186,6 +216,11 @@ CONFIGS = {
     "c2": ("image", (256, 256, 3), (12, 3, 3), 0.1, 100, "f32"),
     "c3": ("video", (144, 176, 3, 50), (8, 3, 8, 3, 8, 3), 0.05, 100, "f32"),
     "c4": ("spectral", (512, 512, 31), (16, 8, 8), 0.05, 80, "bf16"),
+    # the paper's second workload set, at its own shapes (Section 4): a new
+    # color video (500 x 550 x 3 x 24) and a multi-temporal multispectral
+    # image (300 x 300 x 4 bands x 5 dates)
+    "c5": ("video", (500, 550, 3, 24), (8, 3, 8, 3, 8, 3), 0.05, 100, "f32"),
+    "c6": ("multitemporal", (300, 300, 4, 5), (8, 3, 4, 3, 4, 3), 0.05, 100, "f32"),
 }
 
 
@@ -198,6 +233,8 @@ def _truth(kind, rng, dims):
         return video(rng, dims[0], dims[1], dims[3])
     if kind == "spectral":
         return multispectral(rng, dims[0], dims[1], dims[2])
+    if kind == "multitemporal":
+        return multitemporal(rng, dims[0], dims[1], dims[2], dims[3])
     raise ValueError(kind)
 
 
