@@ -79,6 +79,13 @@ typedef struct {
                                        1: for N = 4 alternate (1,2,3,4) and
                                        (3,4,1,2) so a cached pair carries over
                                        (Algorithm 2's permuted order)        */
+  double extrap_alpha;              /* asymmetric extrapolation (Section 4.2,
+                                       multi-temporal images): after each
+                                       factor's subproblem, A_k <- A_k +
+                                       alpha (A_k - beta A_k^t), A_k^t the
+                                       factor the subproblem started from.
+                                       0 = off; otherwise 0 < alpha < 1     */
+  double extrap_beta;               /* beta in [0, 1] (the paper uses 0.5)   */
 } fctn_desc;
 
 /* Per-sweep scalars (Algorithm 1 stopping rule; Section 3.5 objective f). */
@@ -173,8 +180,10 @@ fctn_status fctn_step_gram_rhs(fctn_plan_t plan, int32_t k, double* G_dev,
                                double* B_dev);
 
 /* Solve eq. 5 for mode k given G_dev, B_dev (layouts as above, float64) and
- * store the result as factor k (eq. 8-9).  Returns tr(A^T L_k A) of the new
- * factor in *trace_host if not NULL (synchronizes). */
+ * store the result as factor k (eq. 8-9), extrapolated against the previous
+ * factor k when the descriptor's extrap_alpha > 0 (Section 4.2).  Returns
+ * tr(A^T L_k A) of the stored factor in *trace_host if not NULL
+ * (synchronizes). */
 fctn_status fctn_step_solve(fctn_plan_t plan, int32_t k, const double* G_dev,
                             const double* B_dev, double* trace_host);
 

@@ -126,6 +126,8 @@ fctn_status validate(const fctn_desc* d) {
   if (d->precision < FCTN_F64 || d->precision > FCTN_BF16X3) return FCTN_E_INVALID;
   if (d->reuse != 0 && d->reuse != 1) return FCTN_E_INVALID;
   if (d->order_policy != 0 && d->order_policy != 1) return FCTN_E_INVALID;
+  if (!(d->extrap_alpha >= 0.0 && d->extrap_alpha < 1.0)) return FCTN_E_INVALID;
+  if (!(d->extrap_beta >= 0.0 && d->extrap_beta <= 1.0)) return FCTN_E_INVALID;
   if (N != 3 && N != 4) return FCTN_E_UNSUPPORTED;
   return FCTN_OK;
 }
@@ -594,9 +596,20 @@ fctn_status solve(fctn_plan_s* P, int k, const double* G, const double* B) {
              launch_solve_classes(G, (int32_t)m.Ik, (int32_t)m.s, P->d.lambda[k],
                                   P->d.delta[k], P->d.rho, P->At,
                                   P->trace_part + (size_t)k * P->max_cls, P->st));
-  FCTN_TIMED(P, FCTN_STAGE_TRANSFORM, tr_flops, tr_bytes + 2.0 * m.Ik * m.s * P->es,
+  // with the asymmetric extrapolation the epilogue also reads the proximal
+  // centre A_k^t (overwritten in place), and the trace term the solve wrote
+  // for the un-extrapolated factor is recomputed for the new one
+  const bool ext = P->d.extrap_alpha > 0.0;
+  FCTN_TIMED(P, FCTN_STAGE_TRANSFORM, tr_flops + (ext ? 3.0 * m.Ik * m.s : 0.0),
+             tr_bytes + 2.0 * m.Ik * m.s * P->es + (ext ? 8.0 * m.Ik * m.s : 0.0),
              launch_backtransform(P->prec, P->Q[k], P->At, (int32_t)m.Ik, (int32_t)m.s,
-                                  m.spost, P->A64[k], P->Aw[k], P->Au[k], P->st));
+                                  m.spost, P->d.extrap_alpha, P->d.extrap_beta, P->A64[k],
+                                  P->Aw[k], P->Au[k], P->st));
+  if (ext)
+    FCTN_TIMED(P, FCTN_STAGE_TRANSFORM, 4.0 * m.Ik * m.s, 8.0 * m.Ik * m.s,
+               launch_factor_trace(P->A64[k], (int32_t)m.Ik, (int32_t)m.s, m.spost,
+                                   P->d.delta[k], (int32_t)m.ncls,
+                                   P->trace_part + (size_t)k * P->max_cls, P->st));
   P->fver[k]++;
   return FCTN_OK;
 }

@@ -374,6 +374,7 @@ template <int EPI, typename W>
 __global__ void __launch_bounds__(256) gemm64_k(const double* __restrict__ A,
                                                 const double* __restrict__ X, int M, int K,
                                                 int N, double* __restrict__ C, int64_t spost,
+                                                double alpha, double beta,
                                                 double* __restrict__ A64, W* __restrict__ Aw,
                                                 W* __restrict__ Au) {
   typedef Mfma<double> MM;
@@ -409,11 +410,15 @@ __global__ void __launch_bounds__(256) gemm64_k(const double* __restrict__ A,
     for (int r = 0; r < 4; ++r) {
       const int i = i0 + MM::row(lane, r);
       if (i < M) {
-        const double v = ((acc[r] + part[0][r][lane]) + part[1][r][lane]) + part[2][r][lane];
+        const double vs = ((acc[r] + part[0][r][lane]) + part[1][r][lane]) + part[2][r][lane];
         if constexpr (EPI == 0) {
-          C[(int64_t)i * N + j] = v;
+          C[(int64_t)i * N + j] = vs;
         } else {
           const int64_t f = (j / spost) * ((int64_t)M * spost) + (int64_t)i * spost + j % spost;
+          double v = vs;
+          // asymmetric extrapolation (Section 4.2) against the factor this
+          // subproblem started from, still held in A64
+          if (alpha > 0.0) v = vs + alpha * (vs - beta * A64[f]);
           A64[f] = v;
           Aw[f] = (W)v;
           Au[(int64_t)i * N + j] = (W)v;
@@ -427,21 +432,62 @@ static inline int gemm_blocks(int32_t M, int32_t N) { return ((M + 15) / 16) * (
 
 hipError_t launch_project(const double* Qt, const double* B, int32_t Ik, int32_t s, double* Bt,
                           hipStream_t st) {
-  gemm64_k<0, double><<<gemm_blocks(Ik, s), 256, 0, st>>>(Qt, B, Ik, Ik, s, Bt, 1, nullptr,
-                                                          nullptr, nullptr);
+  gemm64_k<0, double><<<gemm_blocks(Ik, s), 256, 0, st>>>(Qt, B, Ik, Ik, s, Bt, 1, 0.0, 0.0,
+                                                          nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_backtransform(int prec, const double* Q, const double* At, int32_t Ik,
-                                int32_t s, int64_t spost, double* A64, void* Aw, void* Au,
-                                hipStream_t st) {
+                                int32_t s, int64_t spost, double alpha, double beta,
+                                double* A64, void* Aw, void* Au, hipStream_t st) {
   const int nb = gemm_blocks(Ik, s);
   if (prec == P_F64)
-    gemm64_k<1, double><<<nb, 256, 0, st>>>(Q, At, Ik, Ik, s, nullptr, spost, A64,
+    gemm64_k<1, double><<<nb, 256, 0, st>>>(Q, At, Ik, Ik, s, nullptr, spost, alpha, beta, A64,
                                             (double*)Aw, (double*)Au);
   else
-    gemm64_k<1, float><<<nb, 256, 0, st>>>(Q, At, Ik, Ik, s, nullptr, spost, A64, (float*)Aw,
-                                           (float*)Au);
+    gemm64_k<1, float><<<nb, 256, 0, st>>>(Q, At, Ik, Ik, s, nullptr, spost, alpha, beta, A64,
+                                           (float*)Aw, (float*)Au);
+  return hipGetLastError();
+}
+
+// tr(A^T L A) = sum over the s columns a of delta ||a||^2 + sum_i (a_i -
+// a_{i+1 mod I})^2, the quadratic form of L = (2 + delta) I - S - S^T
+// (Section 3.1) written with periodic first differences.  One workgroup: the
+// factor holds at most a few hundred thousand entries.
+__global__ void __launch_bounds__(1024) factor_trace_k(const double* __restrict__ A64, int Ik,
+                                                      int s, int64_t spost, double delta,
+                                                      int ncls, double* __restrict__ trace_part) {
+  __shared__ double red[16];
+  double t = 0.0;
+  for (int j = threadIdx.x; j < s; j += 1024) {
+    const double* col = A64 + (j / spost) * ((int64_t)Ik * spost) + j % spost;
+    const double a0 = col[0];
+    double prev = a0, sq = 0.0, df = 0.0;
+    for (int i = 1; i < Ik; ++i) {
+      const double a = col[(int64_t)i * spost];
+      sq += prev * prev;
+      df += (prev - a) * (prev - a);
+      prev = a;
+    }
+    sq += prev * prev;
+    df += (prev - a0) * (prev - a0);
+    t += delta * sq + df;
+  }
+  t = wave_sum(t);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < 16; ++w) tot += red[w];
+    trace_part[0] = tot;
+  }
+  for (int c = 1 + threadIdx.x; c < ncls; c += 1024) trace_part[c] = 0.0;
+}
+
+hipError_t launch_factor_trace(const double* A64, int32_t Ik, int32_t s, int64_t spost,
+                               double delta, int32_t ncls, double* trace_part, hipStream_t st) {
+  factor_trace_k<<<1, 1024, 0, st>>>(A64, Ik, s, spost, delta, ncls, trace_part);
   return hipGetLastError();
 }
 

@@ -112,9 +112,18 @@ hipError_t launch_project(const double* Qt, const double* B, int32_t Ik, int32_t
 hipError_t launch_solve_classes(const double* G, int32_t Ik, int32_t s, double lam,
                                 double delta, double rho, double* At, double* trace_part,
                                 hipStream_t st);
+// A_k = fold(Q a~) into A64 (float64 master), Aw (working precision, factor
+// layout) and Au (working precision, mode-k unfolding).  alpha > 0 applies the
+// asymmetric extrapolation A <- (1 + alpha) A - alpha beta A64_old elementwise,
+// reading the previous factor from A64 before overwriting it.
 hipError_t launch_backtransform(int prec, const double* Q, const double* At, int32_t Ik,
-                                int32_t s, int64_t spost, double* A64, void* Aw, void* Au,
-                                hipStream_t st);
+                                int32_t s, int64_t spost, double alpha, double beta,
+                                double* A64, void* Aw, void* Au, hipStream_t st);
+// tr(A_(k)^T L_k A_(k)) of the float64 factor, written to trace_part[0]
+// (trace_part[1 .. ncls-1] are cleared), in the slots the class solves use.
+hipError_t launch_factor_trace(const double* A64, int32_t Ik, int32_t s, int64_t spost,
+                               double delta, int32_t ncls, double* trace_part,
+                               hipStream_t st);
 hipError_t launch_reconstruct(int prec, const MGen& mg, const void* Au, void* Z,
                               const XView& xv, const RecGeom& g, hipStream_t st);
 // blocks of x_update_k for n elements (one 16-byte vector per thread)

@@ -39,6 +39,8 @@ class fctn_desc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("reuse", ctypes.c_int32),
         ("order_policy", ctypes.c_int32),
+        ("extrap_alpha", ctypes.c_double),
+        ("extrap_beta", ctypes.c_double),
     ]
 
 
@@ -151,7 +153,8 @@ def fctn_status_str(status):
 
 
 def make_desc(dims, ranks, lam=1e-2, delta=0.5, rho=0.1, precision="f32", reuse=True,
-              order_policy=1):
+              order_policy=1, extrapolation=None):
+    """extrapolation: None, or (alpha, beta) of the asymmetric extrapolation."""
     d = fctn_desc()
     N = len(dims)
     d.order = N
@@ -168,6 +171,9 @@ def make_desc(dims, ranks, lam=1e-2, delta=0.5, rho=0.1, precision="f32", reuse=
     d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     d.reuse = int(bool(reuse))
     d.order_policy = int(order_policy)
+    if extrapolation is not None:
+        d.extrap_alpha = float(extrapolation[0])
+        d.extrap_beta = float(extrapolation[1])
     return d
 
 
@@ -195,13 +201,14 @@ class Plan:
     """One completion problem resident on the GPU (torch-owned workspace)."""
 
     def __init__(self, dims, ranks, lam=1e-2, delta=0.5, rho=0.1, precision="f32", reuse=True,
-                 order_policy=1, device="cuda:0", stream=None):
+                 order_policy=1, device="cuda:0", stream=None, extrapolation=None):
         import torch
         self.torch = torch
         self.dims = tuple(int(v) for v in dims)
         self.ranks = tuple(int(r) for r in ranks)
         self.precision = precision
-        self.desc = make_desc(dims, ranks, lam, delta, rho, precision, reuse, order_policy)
+        self.desc = make_desc(dims, ranks, lam, delta, rho, precision, reuse, order_policy,
+                              extrapolation)
         self.ws_bytes = fctn_workspace_bytes(self.desc)
         if self.ws_bytes == 0:
             raise FctnError(E_UNSUPPORTED if 2 <= len(dims) <= 8 else E_INVALID, "fctn_workspace_bytes")
@@ -384,12 +391,13 @@ class Server:
         self._done = (fctn_completion * 256)()
 
     def submit(self, tag, dims, ranks, Y, mask, A0, sweeps, lam=1e-2, delta=0.5, rho=0.1,
-               precision="bf16x3", reuse=True, order_policy=1):
+               precision="bf16x3", reuse=True, order_policy=1, extrapolation=None):
         """Queue a request.  Y, mask: device tensors (elem, uint8); A0: float64
         device tensor with every factor back to back.  The completed X is
         returned by step() in a tensor allocated here."""
         torch = self.torch
-        desc = make_desc(dims, ranks, lam, delta, rho, precision, reuse, order_policy)
+        desc = make_desc(dims, ranks, lam, delta, rho, precision, reuse, order_policy,
+                         extrapolation)
         elem = torch.float64 if precision == "f64" else torch.float32
         X = torch.empty(tuple(int(d) for d in dims), dtype=elem, device=self.device)
         req = fctn_request()

@@ -45,9 +45,14 @@ def test_workspace_bytes_and_validation(F):
     # invalid descriptors give 0
     bad = [F.make_desc((32, 0, 8), (3, 3, 3)), F.make_desc((32, 32, 8), (3, 0, 3)),
            F.make_desc((32, 32, 8), (3, 3, 3), rho=0.0),
-           F.make_desc((32, 32, 8), (3, 3, 3), lam=-1.0)]
+           F.make_desc((32, 32, 8), (3, 3, 3), lam=-1.0),
+           F.make_desc((32, 32, 8), (3, 3, 3), extrapolation=(1.0, 0.5)),
+           F.make_desc((32, 32, 8), (3, 3, 3), extrapolation=(-0.1, 0.5)),
+           F.make_desc((32, 32, 8), (3, 3, 3), extrapolation=(0.5, 1.5))]
     for b in bad:
         assert F.fctn_workspace_bytes(b) == 0
+    assert F.fctn_workspace_bytes(F.make_desc((32, 32, 8), (3, 3, 3), precision="f64",
+                                              extrapolation=(0.5, 0.5))) == n
     # valid for the method, outside this build: N = 5, rank products above 192
     assert F.fctn_workspace_bytes(F.make_desc((3,) * 5, (2,) * 10)) == 0
     assert F.fctn_workspace_bytes(F.make_desc((8, 8, 8), (16, 16, 2))) == 0
@@ -93,3 +98,31 @@ def test_every_small_shape_is_supported(F):
         if F.fctn_workspace_bytes(F.make_desc(dims, (2,) * 6, precision="f32")) == 0:
             bad.append(dims)
     assert not bad
+
+
+def test_struct_layouts_match_header(F, tmp_path):
+    # the ctypes mirrors of the C structs have the size and field offsets a C
+    # compiler gives the header's declarations
+    structs = {"fctn_desc": F.fctn_desc, "fctn_sweep_stats": F.fctn_sweep_stats,
+               "fctn_stats": F.fctn_stats, "fctn_request": F.fctn_request,
+               "fctn_completion": F.fctn_completion}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fctn.h"',
+             'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for fld, _ in cls._fields_:
+            cf = "lambda" if fld == "lambda_" else fld
+            lines.append(f'  printf("{name}.{fld} %zu\\n", offsetof({name}, {cf}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fld, _ in cls._fields_:
+            assert int(got[f"{name}.{fld}"]) == getattr(cls, fld).offset, (name, fld)
