@@ -38,6 +38,16 @@ later in the sweep, FCTN(A^{t+1}) in the X step and the next sweep's proximal
 centre all see the extrapolated factor.  The PAM objective is then no longer
 monotone.
 
+Rank-increasing schedule (Algorithms 1-2 take a maximal FCTN-rank and start
+from rank ones; the growth rule itself is deferred to the paper's reference
+[Zheng2022], so the rule here is this build's reading): after a sweep whose
+relative change is below tau, every bond rank below its maximum grows by one.
+Each grown bond (i, j), i < j, gets a new slice in both factors: factor i's new
+entries are fresh draws (standard normal, like the initial factors), factor
+j's are zero, so FCTN(A) and X are unchanged by the growth itself; the next
+sweep starts a new run (sweep counter, and with it the alternating order,
+restarting at zero).
+
 Initial X is P_Omega(Y): the observed tensor is zero off Omega by definition
 of a partial observation (Section 1), so Algorithm 1's X^(1) = Y is read as
 P_Omega(Y); values of Y off Omega never enter any arithmetic.
@@ -163,7 +173,8 @@ def x_update(X, Z, mask, rho):
 
 
 def complete(Y, mask, ranks, lam, delta, rho, sweeps, A0, tol=0.0, reuse=True,
-             order_policy=0, record_blocks=False, counters=None, extrapolation=None):
+             order_policy=0, record_blocks=False, counters=None, extrapolation=None,
+             X0=None, t0=0):
     """Run PAM (Algorithm 1 if reuse is False, Algorithm 2 if True).
 
     Y, mask: observed tensor and boolean Omega of shape I_1 x .. x I_N.
@@ -173,6 +184,8 @@ def complete(Y, mask, ranks, lam, delta, rho, sweeps, A0, tol=0.0, reuse=True,
     objective and, with record_blocks, the objective after every block.
     counters: optional list that receives one FlopCounter per sweep.
     extrapolation: None, or (alpha, beta) of the asymmetric extrapolation.
+    X0: the starting X (equal to Y on Omega); None starts from P_Omega(Y).
+    t0: index of the first sweep (selects the sweep order).
     """
     Y = np.asarray(Y, dtype=np.float64)
     mask = np.asarray(mask, dtype=bool)
@@ -182,14 +195,14 @@ def complete(Y, mask, ranks, lam, delta, rho, sweeps, A0, tol=0.0, reuse=True,
     delta = np.broadcast_to(np.asarray(delta, dtype=np.float64), (N,))
     shapes = tensor.factor_shapes(dims, ranks)
     factors = [np.array(a, dtype=np.float64).reshape(s) for a, s in zip(A0, shapes)]
-    X = np.where(mask, Y, 0.0)
+    X = np.where(mask, Y, 0.0) if X0 is None else np.array(X0, dtype=np.float64)
     cache = PairCache()
     versions = [0] * N
     stats = {"rel_change": [], "objective": [], "blocks": [], "sweeps_done": 0}
 
     for t in range(sweeps):
         counter = FlopCounter()
-        order = sweep_order(N, t, order_policy)
+        order = sweep_order(N, t0 + t, order_policy)
         Mk = None
         for k in order:
             Mk = subnetwork_M(factors, k, reuse, cache, versions, counter)
@@ -229,4 +242,58 @@ def complete(Y, mask, ranks, lam, delta, rho, sweeps, A0, tol=0.0, reuse=True,
             counters.append(counter)
         if tol > 0 and rel <= tol:
             break
+    return X, factors, stats
+
+
+def grow_factors(factors, dims, ranks_old, ranks_new, fills):
+    """Embed factors of FCTN-rank ranks_old into ranks_new (elementwise >=).
+    Factor k keeps its old entries; an entry whose index along some bond
+    (j, k), j < k, is a new one is zero; every other new entry (new only along
+    bonds (k, j), j > k) is taken from fills[k], an array of the new shape."""
+    N = len(dims)
+    Ro = tensor.rank_matrix(ranks_old, N)
+    new_shapes = tensor.factor_shapes(dims, ranks_new)
+    out = []
+    for k in range(N):
+        a = np.array(fills[k], dtype=np.float64).reshape(new_shapes[k]).copy()
+        for j in range(k):
+            idx = [slice(None)] * N
+            idx[j] = slice(Ro[j][k], None)
+            a[tuple(idx)] = 0.0
+        a[tuple(slice(0, n) for n in factors[k].shape)] = factors[k]
+        out.append(a)
+    return out
+
+
+def complete_rank_increasing(Y, mask, rmax, lam, delta, rho, sweeps, A0, fill, tau=1e-2,
+                             r0=None, reuse=True, order_policy=0, extrapolation=None):
+    """PAM with the rank-increasing schedule above.  A0: factors at the start
+    ranks r0 (default all ones); fill(g, ranks) returns the list of draws for
+    growth event g (0, 1, ..) to ranks `ranks`.  Returns (X, factors, stats)
+    with stats["ranks"][t] the ranks sweep t ran at."""
+    Y = np.asarray(Y, dtype=np.float64)
+    mask = np.asarray(mask, dtype=bool)
+    dims = Y.shape
+    rmax = [int(r) for r in rmax]
+    ranks = [1] * len(rmax) if r0 is None else [int(r) for r in r0]
+    factors = [np.array(a, dtype=np.float64) for a in A0]
+    X = None
+    stats = {"rel_change": [], "objective": [], "ranks": [], "sweeps_done": 0}
+    run_t = 0
+    grown = 0
+    for t in range(sweeps):
+        X, factors, st = complete(Y, mask, ranks, lam, delta, rho, 1, factors, reuse=reuse,
+                                  order_policy=order_policy, extrapolation=extrapolation,
+                                  X0=X, t0=run_t)
+        stats["rel_change"].append(st["rel_change"][0])
+        stats["objective"].append(st["objective"][0])
+        stats["ranks"].append(tuple(ranks))
+        stats["sweeps_done"] = t + 1
+        run_t += 1
+        if st["rel_change"][0] < tau and ranks != rmax and t + 1 < sweeps:
+            new = [min(r + 1, m) for r, m in zip(ranks, rmax)]
+            factors = grow_factors(factors, dims, ranks, new, fill(grown, tuple(new)))
+            ranks = new
+            grown += 1
+            run_t = 0
     return X, factors, stats

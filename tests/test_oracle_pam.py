@@ -262,3 +262,64 @@ def test_extrapolation_first_order_weight():
     assert np.abs(move).max() > 1e-7
     np.testing.assert_allclose(extra, (1.0 + alpha) * move, rtol=1e-4,
                                atol=1e-4 * np.abs(move).max())
+
+
+# --- rank-increasing schedule ----------------------------------------------
+
+from workloads import rank_growth_draws  # noqa: E402
+
+
+@pytest.mark.parametrize("dims,r_old,r_new", [
+    ((3, 4, 2), (1, 1, 1), (2, 2, 2)),
+    ((3, 4, 2), (1, 2, 1), (2, 2, 3)),
+    ((2, 3, 2, 2), (1, 1, 1, 1, 1, 1), (2, 1, 2, 2, 1, 2)),
+])
+def test_grow_factors_leaves_fctn_unchanged(dims, r_old, r_new):
+    # the embedded network equals the old one entry by entry (brute-force
+    # index sum over every bond value), old entries are kept, and the draws
+    # land only where no bond (j, k), j < k, takes a new value
+    rng = np.random.default_rng(3)
+    old = init_factors(rng, dims, r_old)
+    fills = rank_growth_draws(4, dims)(0, r_new)
+    new = pam.grow_factors(old, dims, r_old, r_new, fills)
+    np.testing.assert_allclose(tensor.fctn_bruteforce(new), tensor.fctn_bruteforce(old),
+                               rtol=1e-12, atol=1e-12)
+    N = len(dims)
+    Ro = tensor.rank_matrix(r_old, N)
+    for k in range(N):
+        assert new[k].shape == factor_shapes_of(dims, r_new)[k]
+        np.testing.assert_array_equal(new[k][tuple(slice(0, n) for n in old[k].shape)], old[k])
+        for idx in np.ndindex(new[k].shape):
+            if all(idx[j] < old[k].shape[j] for j in range(N)):
+                continue
+            lower_new = any(idx[j] >= Ro[j][k] for j in range(k))
+            assert new[k][idx] == (0.0 if lower_new else fills[k][idx]), (k, idx)
+
+
+def test_rank_schedule_never_growing_is_fixed_rank():
+    Y, mask, _, _ = _small()
+    dims = Y.shape
+    ones = (1, 1, 1)
+    A0 = init_factors(np.random.default_rng(2), dims, ones)
+    fill = rank_growth_draws(9, dims)
+    X0, F0, s0 = pam.complete(Y, mask, ones, 0.3, 0.5, 0.1, 4, A0)
+    X1, F1, s1 = pam.complete_rank_increasing(Y, mask, (2, 3, 2), 0.3, 0.5, 0.1, 4, A0, fill,
+                                              tau=0.0)
+    np.testing.assert_allclose(X1, X0, rtol=1e-12, atol=1e-14)
+    assert s1["ranks"] == [ones] * 4
+
+
+def test_rank_schedule_grows_to_the_maximum():
+    # tau = inf grows after every sweep: ones, then +1 per bond, capped
+    Y, mask, _, _ = _small()
+    dims = Y.shape
+    A0 = init_factors(np.random.default_rng(2), dims, (1, 1, 1))
+    fill = rank_growth_draws(9, dims)
+    X, F, st = pam.complete_rank_increasing(Y, mask, (2, 4, 3), 0.3, 0.5, 0.1, 6, A0, fill,
+                                            tau=np.inf)
+    assert st["ranks"] == [(1, 1, 1), (2, 2, 2), (2, 3, 3), (2, 4, 3), (2, 4, 3), (2, 4, 3)]
+    assert [f.shape for f in F] == factor_shapes_of(dims, (2, 4, 3))
+    np.testing.assert_array_equal(X[mask], Y[mask])
+    # at fixed ranks the objective does not increase
+    obj = st["objective"]
+    assert obj[4] <= obj[3] * (1 + 1e-12) and obj[5] <= obj[4] * (1 + 1e-12)

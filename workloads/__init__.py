@@ -2,7 +2,8 @@
 GPU-side tests and by bench.py.
 
 This package holds input generation only: ground-truth tensors, Bernoulli
-masks, observed tensors and the N(0, 1) initial factors.  It performs none of
+masks, observed tensors, the N(0, 1) initial factors and the N(0, 1) draws
+for rank growth.  It performs none of
 the completion method's arithmetic (no sub-networks, Gram products, solves
 or X updates) and imports neither the oracle nor the GPU library.
 """
@@ -10,5 +11,5 @@ or X updates) and imports neither the oracle nor the GPU library.
 from .generators import (  # noqa: F401
     CONFIGS, Problem, make_problem, init_factors, bernoulli_mask,
     factor_shapes_of, lowrank_order3, color_image, video, multispectral,
-    serving_requests,
+    multitemporal, serving_requests, rank_growth_draws,
 )

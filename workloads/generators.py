@@ -47,6 +47,16 @@ def init_factors(rng, dims, ranks):
     return [rng.standard_normal(s) for s in factor_shapes_of(dims, ranks)]
 
 
+def rank_growth_draws(seed, dims):
+    """Draws for the rank-increasing schedule: fill(g, ranks) returns N(0, 1)
+    float64 arrays with the factor shapes at `ranks`, from a PCG64 stream keyed
+    by (seed, g), so both sides of a comparison see the same values."""
+    def fill(g, ranks):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 77, g])))
+        return [rng.standard_normal(s) for s in factor_shapes_of(dims, ranks)]
+    return fill
+
+
 def bernoulli_mask(rng, shape, sr):
     """Omega: each entry observed independently with probability sr (uint8)."""
     return (rng.random(shape) < sr).astype(np.uint8)
