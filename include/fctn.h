@@ -137,6 +137,18 @@ fctn_status fctn_set_observed(fctn_plan_t plan, const void* Y_dev,
 /* Overwrite X (elem tensor on the device); for step-level checks. */
 fctn_status fctn_set_x(fctn_plan_t plan, const void* X_dev);
 
+/* Rank growth (Algorithms 1-2 start from rank ones and grow to the maximal
+ * FCTN-rank; the growth rule is deferred to the paper's reference [Zheng2022]).
+ * `to` is a plan with the same order, dims and precision as `from` and every
+ * bond rank >= from's.  Copies from's X and observed mask into `to` and embeds
+ * from's float64 factors: old entries are kept; an entry whose index along a
+ * bond (j, k), j < k, is new is zero; every other new entry of factor k is
+ * read from fill_dev (float64, the factors at to's ranks back to back, as for
+ * fctn_set_factors_dev).  FCTN(A) and X are unchanged by the growth.  Waits
+ * for from's stream, runs on to's stream and synchronizes it, so `from` may be
+ * destroyed on return.  `to` starts at sweep 0 (its cached pairs are rebuilt). */
+fctn_status fctn_regrow(fctn_plan_t to, fctn_plan_t from, const double* fill_dev);
+
 /* Run `nsweeps` PAM sweeps (Algorithm 1 or 2 by desc.reuse).  If stats_host
  * is not NULL it receives the scalars of the last sweep (synchronizes). */
 fctn_status fctn_sweep(fctn_plan_t plan, int32_t nsweeps,

@@ -1,8 +1,8 @@
 """MI355X-native trace-regularized FCTN tensor completion (PAM).
 
 The compute path is libfctn.so (hand-written HIP for gfx950, C ABI in
-include/fctn.h); ``fctn`` is its ctypes binding and ``serve`` a request
-loop on top of it.
+include/fctn.h); ``fctn`` is its ctypes binding, ``serve`` a request loop on
+top of it and ``schedule`` the rank-increasing driver.
 """
 
 from .fctn import (  # noqa: F401
@@ -10,3 +10,4 @@ from .fctn import (  # noqa: F401
     sweep_many, factor_shape, lib, LIB_PATH,
 )
 from . import serve  # noqa: F401
+from .schedule import complete_rank_increasing  # noqa: F401

@@ -846,6 +846,55 @@ fctn_status fctn_set_x(fctn_plan_t P, const void* X_dev) {
   return FCTN_OK;
 }
 
+fctn_status fctn_regrow(fctn_plan_t to, fctn_plan_t from, const double* fill_dev) {
+  if (!to || !from || !fill_dev || to == from) return FCTN_E_INVALID;
+  if (to->sticky != FCTN_OK) return to->sticky;
+  if (from->sticky != FCTN_OK) return from->sticky;
+  if (to->N != from->N || to->prec != from->prec) return FCTN_E_INVALID;
+  const int N = to->N;
+  for (int k = 0; k < N; ++k)
+    if (to->dims[k] != from->dims[k]) return FCTN_E_INVALID;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      if (i != j && to->R[i][j] < from->R[i][j]) return FCTN_E_INVALID;
+  // from's pending work (its X and factors) before to's stream reads them
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ev, from->st) != hipSuccess || hipStreamWaitEvent(to->st, ev, 0) != hipSuccess) {
+    if (ev) hipEventDestroy(ev);
+    to->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  bool ok = hipMemcpyAsync(to->X, from->X, to->numel * to->es, hipMemcpyDeviceToDevice,
+                           to->st) == hipSuccess &&
+            hipMemcpyAsync(to->bits, from->bits, ((to->numel + 63) / 64) * 2 * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, to->st) == hipSuccess;
+  int64_t off = 0;
+  for (int k = 0; k < N && ok; ++k) {
+    RegrowDesc d{};
+    d.N = N;
+    for (int j = 0; j < N; ++j) {
+      d.shape_old[j] = j == k ? from->dims[k] : from->R[k][j];
+      d.shape_new[j] = j == k ? to->dims[k] : to->R[k][j];
+      if (j < k) d.zero_modes |= 1u << j;
+    }
+    ok = launch_regrow(from->A64[k], fill_dev + off, to->A64[k], d, to->st) == hipSuccess;
+    const ModeInfo& m = to->mode[k];
+    ok = ok && launch_cast_factor(to->prec, to->A64[k], to->Aw[k], to->Au[k], (int32_t)m.Ik,
+                                  (int32_t)m.s, m.spost, to->st) == hipSuccess;
+    to->fver[k]++;
+    off += to->fnum[k];
+  }
+  to->pvalid[0] = to->pvalid[1] = false;
+  ok = ok && hipStreamSynchronize(to->st) == hipSuccess;
+  hipEventDestroy(ev);
+  if (!ok) {
+    to->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  return FCTN_OK;
+}
+
 fctn_status fctn_sweep(fctn_plan_t P, int32_t nsweeps, fctn_sweep_stats* stats_host) {
   if (!P || nsweeps < 0) return FCTN_E_INVALID;
   if (P->sticky != FCTN_OK) return P->sticky;

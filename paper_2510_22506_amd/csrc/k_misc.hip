@@ -112,6 +112,43 @@ hipError_t launch_cast_factor(int prec, const double* A64, void* Aw, void* Au, i
 }
 
 // ---------------------------------------------------------------------------
+// Rank growth: factor k at larger bond ranks.  Entry (m_1 .. m_N) of the new
+// factor (last mode fastest) is the old entry when every index is inside the
+// old shape; zero when an index along a bond (j, k), j < k (bit j of
+// zero_modes) is a new one; otherwise the caller's draw fill[e].  Zero slices
+// on the higher-index side of each grown bond keep FCTN(A) unchanged.
+// ---------------------------------------------------------------------------
+__global__ void regrow_k(const double* __restrict__ old, const double* __restrict__ fill,
+                         double* __restrict__ out, RegrowDesc d, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = e, off = 0, stride = 1;
+    bool inside = true, zero = false;
+    for (int j = d.N - 1; j >= 0; --j) {
+      const int64_t m = rem % d.shape_new[j];
+      rem /= d.shape_new[j];
+      if (m >= d.shape_old[j]) {
+        inside = false;
+        if ((d.zero_modes >> j) & 1) zero = true;
+      }
+      off += m * stride;
+      stride *= d.shape_old[j];
+    }
+    out[e] = inside ? old[off] : (zero ? 0.0 : fill[e]);
+  }
+}
+
+hipError_t launch_regrow(const double* old, const double* fill, double* out,
+                         const RegrowDesc& d, hipStream_t st) {
+  int64_t n = 1;
+  for (int j = 0; j < d.N; ++j) n *= d.shape_new[j];
+  if (n == 0) return hipSuccess;
+  const int nb = (int)(cdiv(n, 256) < 1024 ? cdiv(n, 256) : 1024);
+  regrow_k<<<nb, 256, 0, st>>>(old, fill, out, d, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Real orthonormal eigenbasis of the circulant L = (2 + delta) I - S - S^T:
 // column 0 is constant; columns 2c-1, 2c are the cosine and sine of frequency
 // c (1 <= c < n/2); for even n the last column alternates in sign.  Column

@@ -83,6 +83,15 @@ struct PairDesc {
 // precision codes shared with the C ABI
 enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
 
+// one factor's shapes before and after a rank growth (last mode fastest);
+// bit j of zero_modes: new indices along mode j give zero entries
+struct RegrowDesc {
+  int64_t shape_old[8];
+  int64_t shape_new[8];
+  int32_t N;
+  uint32_t zero_modes;
+};
+
 // per-mode constants of a plan, passed by value to the kernel that stores them
 struct PlanConsts {
   double lam_half[8];
@@ -98,6 +107,8 @@ hipError_t launch_any_flag(const int32_t* part, int n, int32_t* flag, hipStream_
 hipError_t launch_init_observed(int prec, const void* Y, const uint8_t* mask, void* X,
                                 uint32_t* bits, int32_t* bad_part, int64_t n, int nblk,
                                 hipStream_t st);
+hipError_t launch_regrow(const double* old, const double* fill, double* out,
+                         const RegrowDesc& d, hipStream_t st);
 hipError_t launch_cast_factor(int prec, const double* A64, void* Aw, void* Au, int32_t Ik,
                               int32_t s, int64_t spost, hipStream_t st);
 hipError_t launch_build_basis(double* Q, double* Qt, double* lam_col, int32_t n, double delta,

@@ -96,6 +96,7 @@ _SIGS = {
     "fctn_set_observed": (ctypes.c_int, [_P, _P, _P]),
     "fctn_set_factors_dev": (ctypes.c_int, [_P, _P]),
     "fctn_set_x": (ctypes.c_int, [_P, _P]),
+    "fctn_regrow": (ctypes.c_int, [_P, _P, _P]),
     "fctn_sweep": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(fctn_sweep_stats)]),
     "fctn_sweep_many": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32]),
     "fctn_complete": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
@@ -245,6 +246,17 @@ class Plan:
         self._sync_inputs()
         _check(lib().fctn_set_x(self.handle, _ptr(X)), "fctn_set_x")
         self._keep = X
+
+    def regrow_from(self, old, fills):
+        """Take X, the mask and the factors of `old` (same dims and precision,
+        bond ranks <= this plan's), embedding the factors at this plan's ranks;
+        fills: this plan's factor shapes, float64 (list of arrays or one device
+        tensor with every factor back to back), read at the new entries."""
+        if isinstance(fills, (list, tuple)):
+            fills = self.torch.cat([self._dev(f, self.torch.float64).reshape(-1) for f in fills])
+        fills = self._dev(fills, self.torch.float64)
+        self._sync_inputs()
+        _check(lib().fctn_regrow(self.handle, old.handle, _ptr(fills)), "fctn_regrow")
 
     # -- sweeps -------------------------------------------------------------
     def sweep(self, n=1, stats=False):
