@@ -15,9 +15,17 @@ time (HIP events on the plan's stream over the timed region): algorithmic
 flops (or bytes) per launch / average launch time, against MI355X's
 published peak for that kernel's bound.  `serving` is the request-serving
 workload through the continuous-batching server (completions/s, p50/p99
-latency, split bf16 against float32 at saturation).  `cpu_baseline` is the
-float64 oracle on the host cores over a bounded number of sweeps of the same
+latency, split bf16 against float32 at saturation).  `rank_schedule` runs
+the rank-increasing schedule on the same workload (rank ones up to its ranks)
+and times one growth.  `roofline_xpass_large` is the X/mask pass on a 1 GiB
+tensor (larger than the Infinity Cache).  `cpu_baseline` is the float64
+oracle on the host cores over a bounded number of sweeps of the same
 workload.
+
+Other workloads (--workload): c1 low-rank 32x32x8 (float64), c2 color image
+256x256x3, c4 multispectral 512x512x31, c5 new-video 500x550x3x24, c6
+multi-temporal 300x300x4x5 (with the asymmetric extrapolation, as the paper
+runs its multi-temporal images).
 """
 
 import argparse
@@ -202,6 +210,48 @@ def xpass_large(dims=(1024, 1024, 256), launches=10):
     return r
 
 
+def rank_schedule(prob, prec, ext, sweeps=20):
+    """The rank-increasing schedule on the same workload: from rank ones to the
+    workload's ranks, growing after every sweep (tau = inf) until the maximum,
+    then fixed; wall time of the whole run (plans, growth, per-sweep stats) and
+    of one growth (plan creation and fctn_regrow) at the last step."""
+    import numpy as np
+    import torch
+    from paper_2510_22506_amd import Plan, complete_rank_increasing
+    from workloads import init_factors, rank_growth_draws
+    dims, rmax = prob.dims, prob.ranks
+    A0 = init_factors(np.random.default_rng(31), dims, (1,) * len(rmax))
+    fill = rank_growth_draws(32, dims)
+    kw = dict(lam=prob.lam, delta=prob.delta, rho=prob.rho, precision=prec, extrapolation=ext)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p, hist = complete_rank_increasing(dims, rmax, prob.Y, prob.mask, A0, fill, sweeps,
+                                       tau=float("inf"), **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    p.close()
+    # one growth to the maximal ranks, timed alone
+    below = tuple(max(r - 1, 1) for r in rmax)
+    src = Plan(dims, below, **kw)
+    src.set_factors(init_factors(np.random.default_rng(33), dims, below))
+    src.set_observed(prob.Y, prob.mask)
+    src.sweep(1)
+    draws = fill(0, tuple(rmax))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dst = Plan(dims, rmax, **kw)
+    t2 = time.perf_counter()
+    dst.regrow_from(src, draws)
+    t3 = time.perf_counter()
+    src.close()
+    dst.close()
+    return {"sweeps": sweeps, "growths": len(set(h["ranks"] for h in hist)) - 1,
+            "wall_s": wall, "sweeps_per_s": sweeps / wall,
+            "ranks_first_last": [list(hist[0]["ranks"]), list(hist[-1]["ranks"])],
+            "growth_ms": {"plan": (t2 - t1) * 1e3, "regrow": (t3 - t2) * 1e3,
+                          "from": list(below), "to": list(rmax)}}
+
+
 def cpu_baseline(prob, sweeps, ext=None):
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -236,6 +286,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="add the per-stage breakdown")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-rank-schedule", action="store_true",
+                    help="skip the rank-increasing schedule measurement")
     ap.add_argument("--no-xpass-large", action="store_true",
                     help="skip the X/mask pass on a 1 GiB tensor")
     ap.add_argument("--serve-n", type=int, default=256)
@@ -337,6 +389,11 @@ def main():
             line["roofline_xpass_large"] = xpass_large()
         except Exception as e:  # reported, never hides the sweep measurement
             line["roofline_xpass_large"] = {"error": f"{type(e).__name__}: {e}"}
+    if not args.no_rank_schedule:
+        try:
+            line["rank_schedule"] = rank_schedule(prob, prec, ext)
+        except Exception as e:  # reported, never hides the sweep measurement
+            line["rank_schedule"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_serve:
         try:
             line["serving"] = serving(args)
