@@ -75,31 +75,97 @@ __device__ inline void build_tables(const MGen& mg, const TileGeom& tg, const XV
   }
 }
 
+// Batched 2-D gather into LDS.  The calling thread owns the points
+// x = x0 + j sx < nx (the fast axis, along which neighbouring lanes read
+// neighbouring addresses) and y = y0 + i sy < ny, visited i-fastest; it issues
+// kGatherBatch loads before their LDS stores, so that the loads of a batch are
+// in flight together instead of one round trip each.  src(x, y) returns the
+// value (its own bounds decide whether it reads memory); dst(x, y, v) stores.
+constexpr int kGatherBatch = 4;
+
+template <typename T, class Src, class Dst>
+__device__ inline void gather2d(int x0, int sx, int nx, int y0, int sy, int ny, Src src,
+                                Dst dst) {
+  if (x0 >= nx || y0 >= ny) return;
+  const int nA = (nx - x0 + sx - 1) / sx, nB = (ny - y0 + sy - 1) / sy, n = nA * nB;
+  int j = 0, i = 0;
+  for (int n0 = 0; n0 < n; n0 += kGatherBatch) {
+    T v[kGatherBatch];
+    const int js = j, is = i;
+#pragma unroll
+    for (int b = 0; b < kGatherBatch; ++b) {
+      v[b] = T(0);
+      if (n0 + b < n) v[b] = src(x0 + j * sx, y0 + i * sy);
+      if (++i == nB) {
+        i = 0;
+        ++j;
+      }
+    }
+    // the same points again for the stores (fewer live registers than
+    // keeping their coordinates)
+    j = js;
+    i = is;
+#pragma unroll
+    for (int b = 0; b < kGatherBatch; ++b) {
+      if (n0 + b < n) dst(x0 + j * sx, y0 + i * sy, v[b]);
+      if (++i == nB) {
+        i = 0;
+        ++j;
+      }
+    }
+  }
+}
+
 // Stage one operand slab S(kap, p) = F[tab[p].off + base + kap * f_k] (zero
 // in the padding and beyond the tensor edge: tab[p].cl >= lim).  Lanes run
-// along the slab's contiguous index (2^lw of them).
-template <typename T>
+// along the slab's contiguous index (2^lw of them).  kBatched: loads issued in
+// batches (gather2d); the float32 Gram kernel, which has no registers to
+// spare at two workgroups per CU, stages one element per thread at a time.
+template <typename T, bool kBatched>
 __device__ inline void stage_slab(const T* __restrict__ F, int64_t base, int64_t f_k, int K,
                                   int Kp, int Pp, int s_k, int s_p, int lw,
                                   const SlabRow* __restrict__ tab, int64_t lim,
                                   T* __restrict__ S, int tid, int nth) {
   const int lanes = 1 << lw, lane = tid & (lanes - 1), grp = tid >> lw, ngrp = nth >> lw;
-  if (s_k == 1) {                       // [p][kap]: lanes along kap
-    for (int p = grp; p < Pp; p += ngrp) {
-      const SlabRow r = tab[p];
-      const bool okp = r.cl < lim;
-      const T* src = F + base + r.off;
-      for (int k = lane; k < Kp; k += lanes)
-        S[p * s_p + k] = (okp && k < K) ? src[(int64_t)k * f_k] : T(0);
-    }
-  } else {                              // [kap][p]: lanes along p
-    for (int k = grp; k < Kp; k += ngrp) {
-      const bool okk = k < K;
-      for (int p = lane; p < Pp; p += lanes) {
+  const T* Fb = F + base;
+  if constexpr (!kBatched) {
+    if (s_k == 1) {                     // [p][kap]: lanes along kap
+      for (int p = grp; p < Pp; p += ngrp) {
         const SlabRow r = tab[p];
-        S[k * s_k + p] = (okk && r.cl < lim) ? F[base + r.off + (int64_t)k * f_k] : T(0);
+        const bool okp = r.cl < lim;
+        const T* src = Fb + r.off;
+        for (int k = lane; k < Kp; k += lanes)
+          S[p * s_p + k] = (okp && k < K) ? src[(int64_t)k * f_k] : T(0);
+      }
+    } else {                            // [kap][p]: lanes along p
+      for (int k = grp; k < Kp; k += ngrp) {
+        const bool okk = k < K;
+        for (int p = lane; p < Pp; p += lanes) {
+          const SlabRow r = tab[p];
+          S[k * s_k + p] = (okk && r.cl < lim) ? Fb[r.off + (int64_t)k * f_k] : T(0);
+        }
       }
     }
+  } else if (s_k == 1) {                // [p][kap]: lanes along kap
+    gather2d<T>(
+        lane, lanes, Kp, grp, ngrp, Pp,
+        [&](int k, int p) {
+          const SlabRow r = tab[p];
+          T v = T(0);
+          if (r.cl < lim && k < K) v = Fb[r.off + (int64_t)k * f_k];
+          return v;
+        },
+        [&](int k, int p, T v) { S[p * s_p + k] = v; });
+  } else {                              // [kap][p]: lanes along p
+    gather2d<T>(
+        lane, lanes, Pp, grp, ngrp, Kp,
+        [&](int p, int k) {
+          const SlabRow r = tab[p];
+          T v = T(0);
+          if (r.cl < lim && k < K) v = Fb[r.off + (int64_t)k * f_k];
+          return v;
+        },
+        [&](int p, int k, T v) { S[k * s_k + p] = v; });
   }
 }
 
@@ -143,20 +209,20 @@ __device__ inline void mgen_mfma(const TileGeom& tg, const T* __restrict__ Us,
                      nwaves);
 }
 
-template <typename T>
+template <typename T, bool kBatched>
 __device__ inline void stage_operands(const MGen& mg, const TileGeom& tg, const T* U, const T* V,
                                       int64_t tu, int64_t tv, int64_t& cur_tu, int64_t& cur_tv,
                                       T* Us, T* Vs, const SlabRow* ptab, const SlabRow* qtab,
                                       int tid, int nth) {
   if (tu != cur_tu) {
     const int64_t cu0 = tu * tg.TCu;
-    stage_slab<T>(U, cu0 * mg.u_cu, mg.u_k, mg.K, tg.Kp, tg.Pp, tg.us_k, tg.us_p, tg.u_lw, ptab,
+    stage_slab<T, kBatched>(U, cu0 * mg.u_cu, mg.u_k, mg.K, tg.Kp, tg.Pp, tg.us_k, tg.us_p, tg.u_lw, ptab,
                   mg.Cu - cu0, Us, tid, nth);
     cur_tu = tu;
   }
   if (tv != cur_tv) {
     const int64_t cv0 = tv * tg.TCv;
-    stage_slab<T>(V, cv0 * mg.v_cv, mg.v_k, mg.K, tg.Kp, tg.Qp, tg.vs_k, tg.vs_q, tg.v_lw, qtab,
+    stage_slab<T, kBatched>(V, cv0 * mg.v_cv, mg.v_k, mg.K, tg.Kp, tg.Qp, tg.vs_k, tg.vs_q, tg.v_lw, qtab,
                   mg.Cv - cv0, Vs, tid, nth);
     cur_tv = tv;
   }
@@ -197,8 +263,10 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
     xrows = (blast - bfirst + 1) * 16;
   }
 
-  int aoff[kTPW], boff[kTPW];
-  bool fromX[kTPW], valid[kTPW];
+  // this wave's output tiles (wave-uniform): bit 0 = A operand from X_(k),
+  // bits 1-10 = row block bi, bits 11-20 = column block bj
+  int tdesc[kTPW];
+  bool valid[kTPW];
   typename MM::acc_t acc[kTPW];
 #pragma unroll
   for (int j = 0; j < kTPW; ++j) {
@@ -206,7 +274,7 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
     valid[j] = t < t1;
     acc[j] = MM::zero();
     int bi = 0, bj = 0;
-    fromX[j] = false;
+    bool fx = false;
     if (valid[j]) {
       if (t < g.nG) {
         upper_tile(t, bi, bj);
@@ -214,11 +282,10 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
         const int tb = t - g.nG;
         bi = tb / g.nbj - ba_lo;
         bj = tb % g.nbj;
-        fromX[j] = true;
+        fx = true;
       }
     }
-    aoff[j] = bi * 16 + (lane & 15);
-    boff[j] = bj * 16 + (lane & 15);
+    tdesc[j] = (fx ? 1 : 0) | (bi << 1) | (bj << 11);
   }
 
   build_tables(mg, tg, &xv, 1, g.ldm, ptab, qtab, ctab, tid, kGramThreads);
@@ -240,8 +307,8 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
   FCTN_GRAM_MARK_INIT
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
-    stage_operands<T>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
-                      kGramThreads);
+    stage_operands<T, false>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
+                             kGramThreads);
     FCTN_GRAM_MARK(0);
     if (xrows > 0) {
       const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
@@ -276,11 +343,13 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
 #pragma unroll
     for (int j = 0; j < kTPW; ++j) {
       if (valid[j]) {
-        const T* Ab = fromX[j] ? Xs : Ms;
-        const int lda = fromX[j] ? ldx : ldm;
+        const int d = tdesc[j];
+        const T* Ab = (d & 1) ? Xs : Ms;
+        const int lda = (d & 1) ? ldx : ldm;
+        const int ao = ((d >> 1) & 1023) * 16 + (lane & 15), bo = (d >> 11) * 16 + (lane & 15);
         for (int kk = 0; kk < tg.tcolp; kk += MM::kStep) {
-          const T a = Ab[(kk + kr) * lda + aoff[j]];
-          const T b = Ms[(kk + kr) * ldm + boff[j]];
+          const T a = Ab[(kk + kr) * lda + ao];
+          const T b = Ms[(kk + kr) * ldm + bo];
           acc[j] = MM::mma(a, b, acc[j]);
         }
       }
@@ -399,21 +468,30 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
 
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
-    stage_operands<float>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
-                          kGramThreads);
+    stage_operands<float, true>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
+                                kGramThreads);
     if (xrows > 0) {
       const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
       const int64_t lim_u = mg.Cu - cu0, lim_v = mg.Cv - cv0;
       const float* xb = X + cu0 * xv.x_cu + cv0 * xv.x_cv + (int64_t)(ba_lo * 16) * xv.x_ik;
       const int xlim = xv.Ik - ba_lo * 16;
-      for (int e = tid; e < tg.tcol * xrows; e += kGramThreads) {
-        int r, c;
-        if (x_rfast) { c = e / xrows; r = e - c * xrows; }
-        else { r = e / tg.tcol; c = e - r * tg.tcol; }
+      auto xsrc = [&](int r, int c) {
         const SlabRow cr = ctab[c];
-        const float v = (cr.cl < lim_u && cr.map < lim_v && r < xlim)
-                            ? xb[cr.off + (int64_t)r * xv.x_ik] : 0.f;
-        put(Xh, Xl, r * ldb + c, v);
+        float v = 0.f;
+        if (cr.cl < lim_u && cr.map < lim_v && r < xlim) v = xb[cr.off + (int64_t)r * xv.x_ik];
+        return v;
+      };
+      if (x_rfast) {
+        const int xl = min(xrows, 16);
+        const int l = tid % xl, grp = tid / xl, ngrp = kGramThreads / xl;
+        gather2d<float>(
+            l, xl, xrows, grp, ngrp, tg.tcol, xsrc,
+            [&](int r, int c, float v) { put(Xh, Xl, r * ldb + c, v); });
+      } else {
+        gather2d<float>(
+            lane, 64, tg.tcol, wave, kGramWaves, xrows,
+            [&](int c, int r) { return xsrc(r, c); },
+            [&](int c, int r, float v) { put(Xh, Xl, r * ldb + c, v); });
       }
     }
     __syncthreads();
@@ -594,8 +672,8 @@ __global__ void __launch_bounds__(kRecThreads) reconstruct_k(MGen mg, const T* _
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
     const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
-    stage_operands<T>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
-                      kRecThreads);
+    stage_operands<T, true>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
+                            kRecThreads);
     __syncthreads();
     mgen_mfma<T>(tg, Us, Vs, ptab, qtab, Ms, lane, wave, kRecWaves);
     __syncthreads();
