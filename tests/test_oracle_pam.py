@@ -26,6 +26,9 @@ def _objective(X, fs, lam, delta):
 @pytest.mark.parametrize("dims,ranks,k", [
     ((6, 5, 4), (3, 2, 2), 0), ((6, 5, 4), (3, 2, 2), 2),
     ((4, 3, 3, 5), (2, 2, 3, 1, 2, 2), 1), ((4, 3, 3, 5), (2, 2, 3, 1, 2, 2), 3),
+    ((4, 3, 3, 2, 3), (2, 1, 2, 2, 2, 1, 2, 2, 1, 2), 0),
+    ((4, 3, 3, 2, 3), (2, 1, 2, 2, 2, 1, 2, 2, 1, 2), 2),
+    ((4, 3, 3, 2, 3), (2, 1, 2, 2, 2, 1, 2, 2, 1, 2), 4),
 ])
 def test_factor_block_exact_decrease(dims, ranks, k):
     # f_old - f_new = rho ||D||^2 + 1/2 (tr(D G D^T) + lam tr(D^T L D)), D = A_new - A_old
@@ -63,6 +66,7 @@ def test_x_block_exact_decrease():
 @pytest.mark.parametrize("dims,ranks,policy", [
     ((8, 7, 5), (3, 2, 2), 0),
     ((5, 4, 3, 6), (2, 2, 3, 2, 2, 2), 1),
+    ((4, 3, 3, 2, 3), (2, 1, 2, 2, 2, 1, 2, 2, 1, 2), 1),
 ])
 def test_objective_monotone_blockwise(reuse, dims, ranks, policy):
     _, Y, mask, A0 = _rand_problem(dims, ranks, seed=1)

@@ -19,6 +19,8 @@ def _factors(dims, ranks, seed=0):
     ((4, 5, 3), (2, 3, 2)),
     ((3, 4, 2, 3), (2, 2, 2, 2, 2, 2)),
     ((3, 2, 4, 2), (1, 2, 3, 2, 1, 2)),
+    ((2, 3, 2, 2, 2), (2, 1, 2, 2, 1, 2, 1, 2, 2, 1)),
+    ((2, 2, 1, 2, 2, 2), (2, 1, 1, 2, 1, 1, 2, 1, 2, 2, 1, 1, 2, 1, 2)),
 ])
 def test_fctn_matches_bruteforce(dims, ranks):
     fs = _factors(dims, ranks)
@@ -82,6 +84,7 @@ def test_contract_definition3_explicit():
     ((4, 5, 3), (2, 3, 2)),
     ((3, 4, 2, 3), (2, 3, 2, 1, 2, 2)),
     ((2, 3, 2, 2, 3), (2, 1, 2, 2, 1, 2, 1, 2, 2, 1)),
+    ((2, 2, 3, 2, 2, 2), (2, 1, 1, 2, 1, 1, 2, 1, 2, 2, 1, 1, 2, 1, 2)),
 ])
 def test_property1_every_mode(dims, ranks):
     fs = _factors(dims, ranks, seed=4)
