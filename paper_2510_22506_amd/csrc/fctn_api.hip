@@ -40,7 +40,7 @@ struct Carver {
   }
 };
 
-enum Src { SRC_F0 = 0, SRC_P12 = 10, SRC_P34 = 11 };
+enum Src { SRC_F0 = 0, SRC_P12 = 10, SRC_P34 = 11, SRC_G0 = 12, SRC_G1 = 13 };
 
 struct ModeInfo {
   int64_t Ik, s, C, spost;
@@ -50,6 +50,10 @@ struct ModeInfo {
   GramGeom geom;
   RecGeom rg;
   int ncls;
+  // orders N >= 5: the operand groups (0: U, 1: V) that are materialized
+  bool gmat[2];
+  GroupDesc gd[2];
+  int gmem[2][kGroupMaxMembers];
 };
 
 struct ProfRec {
@@ -79,18 +83,18 @@ struct fctn_plan_s {
   int32_t* bad_part;
   int32_t* bad_flag;
   int bad_nblk;
-  double* A64[4];
-  void* Aw[4];
-  void* Au[4];
-  int64_t fnum[4];
+  double* A64[FCTN_MAX_ORDER];
+  void* Aw[FCTN_MAX_ORDER];
+  void* Au[FCTN_MAX_ORDER];
+  int64_t fnum[FCTN_MAX_ORDER];
   void* P[2];
   int64_t pnum[2];
   PairDesc pd[2];
   void* part;
   double *G, *B, *At;
-  double* Q[4];
-  double* Qt[4];
-  double* lamcol[4];
+  double* Q[FCTN_MAX_ORDER];
+  double* Qt[FCTN_MAX_ORDER];
+  double* lamcol[FCTN_MAX_ORDER];
   double* trace_part;
   int max_cls;
   double* lam_half;
@@ -99,9 +103,13 @@ struct fctn_plan_s {
   int xblocks;      // blocks of the X update (one partial triple each)
   double* hist;
   double* scratch_slot;
-  ModeInfo mode[4];
+  ModeInfo mode[FCTN_MAX_ORDER];
+  void* Gb[2];        // orders N >= 5: the current mode's operand groups
+  int64_t gnum[2];
+  int gmode;          // mode the groups were built for (-1: none)
+  int64_t gver[FCTN_MAX_ORDER];
   int64_t sweeps_done;
-  int64_t fver[4];
+  int64_t fver[FCTN_MAX_ORDER];
   int64_t pver[2][2];
   bool pvalid[2];
   fctn_status sticky;
@@ -128,7 +136,7 @@ fctn_status validate(const fctn_desc* d) {
   if (d->order_policy != 0 && d->order_policy != 1) return FCTN_E_INVALID;
   if (!(d->extrap_alpha >= 0.0 && d->extrap_alpha < 1.0)) return FCTN_E_INVALID;
   if (!(d->extrap_beta >= 0.0 && d->extrap_beta <= 1.0)) return FCTN_E_INVALID;
-  if (N != 3 && N != 4) return FCTN_E_UNSUPPORTED;
+  if (N < 3 || N > 6) return FCTN_E_UNSUPPORTED;
   return FCTN_OK;
 }
 
@@ -143,10 +151,135 @@ void fill_ranks(const fctn_desc* d, int R[FCTN_MAX_ORDER][FCTN_MAX_ORDER]) {
   }
 }
 
+// Orders N >= 5.  The other modes split into two groups of consecutive
+// indices, S below T (at k itself when k is inside; in two halves when k is
+// the first or last mode), so that the columns (i_S, i_T) of M_k are a strided
+// view of X and the rows (bonds to k from S, then from T) follow A_k's bond
+// order.  A group of one factor is read in place; a larger group is
+// materialized as G[i_S][bonds to k][cross bonds], the cross bonds (s, t),
+// s in S, t in T, in s-major order on both sides, so that kap runs with one
+// stride through both operands.
+int64_t fstride(const fctn_plan_s* P, int f, int j) {
+  int64_t st = 1;
+  for (int l = P->N - 1; l > j; --l) st *= (l == f) ? P->dims[f] : P->R[f][l];
+  return st;
+}
+
+bool setup_mode_general(fctn_plan_s* P, int k) {
+  const int N = P->N;
+  const int64_t* I = P->dims;
+  int(*R)[FCTN_MAX_ORDER] = P->R;
+  ModeInfo& m = P->mode[k];
+  MGen& g = m.mg;
+  XView& x = m.xv;
+  int S[FCTN_MAX_ORDER], T[FCTN_MAX_ORDER], ns = 0, nt = 0;
+  int split;
+  if (k > 0 && k < N - 1) split = k;            // S = 0..k-1, T = k+1..N-1
+  else if (k == 0) split = 1 + (N - 1) / 2;     // S = 1..split-1
+  else split = (N - 1 + 1) / 2;                 // S = 0..split-1, T = split..N-2
+  for (int j = 0; j < N; ++j) {
+    if (j == k) continue;
+    if (j < split) S[ns++] = j; else T[nt++] = j;
+  }
+  if (ns < 1 || nt < 1 || ns > kGroupMaxMembers || nt > kGroupMaxMembers) return false;
+  int64_t Kc = 1;
+  for (int a = 0; a < ns; ++a)
+    for (int b = 0; b < nt; ++b) Kc *= R[S[a]][T[b]];
+  g.K = (int32_t)Kc;
+  for (int role = 0; role < 2; ++role) {
+    const int* X = role == 0 ? S : T;
+    const int nx = role == 0 ? ns : nt;
+    int64_t Rk = 1, Cx = 1;
+    for (int a = 0; a < nx; ++a) {
+      Rk *= R[X[a]][k];
+      Cx *= I[X[a]];
+    }
+    int64_t r_st, c_st, k_st;
+    m.gmat[role] = nx > 1;
+    if (nx == 1) {
+      const int f = X[0];
+      const int* Y = role == 0 ? T : S;
+      const int ny = role == 0 ? nt : ns;
+      r_st = fstride(P, f, k);
+      c_st = fstride(P, f, f);
+      k_st = fstride(P, f, Y[ny - 1]);
+    } else {
+      r_st = Kc;
+      c_st = Rk * Kc;
+      k_st = 1;
+      GroupDesc& gd = m.gd[role];
+      memset(&gd, 0, sizeof(gd));
+      gd.nm = nx;
+      for (int a = 0; a < nx; ++a) m.gmem[role][a] = X[a];
+      int nd = 0;
+      auto digit = [&](int64_t size) -> int {
+        if (nd >= kGroupMaxDigits) return -1;
+        gd.dsize[nd] = size;
+        return nd++;
+      };
+      for (int a = 0; a < nx; ++a) {          // physical indices
+        const int d = digit(I[X[a]]);
+        if (d < 0) return false;
+        gd.dstride[d][a] = fstride(P, X[a], X[a]);
+      }
+      for (int a = 0; a < nx; ++a) {          // bonds to k
+        const int d = digit(R[X[a]][k]);
+        if (d < 0) return false;
+        gd.dstride[d][a] = fstride(P, X[a], k);
+      }
+      for (int a = 0; a < ns; ++a)            // cross bonds, s-major
+        for (int b = 0; b < nt; ++b) {
+          const int d = digit(R[S[a]][T[b]]);
+          if (d < 0) return false;
+          if (role == 0) gd.dstride[d][a] = fstride(P, S[a], T[b]);
+          else gd.dstride[d][b] = fstride(P, T[b], S[a]);
+        }
+      gd.nd = nd;
+      int ni = 0;
+      gd.inner = 1;
+      for (int a = 0; a < nx; ++a)            // bonds inside the group
+        for (int b = a + 1; b < nx; ++b) {
+          if (ni >= kGroupMaxDigits) return false;
+          gd.isize[ni] = R[X[a]][X[b]];
+          gd.istride[ni][a] = fstride(P, X[a], X[b]);
+          gd.istride[ni][b] = fstride(P, X[b], X[a]);
+          gd.inner *= gd.isize[ni];
+          ++ni;
+        }
+      gd.ni = ni;
+      gd.total = Cx * Rk * Kc;
+      // every offset the kernel forms stays inside its member factor
+      for (int a = 0; a < nx; ++a) {
+        int64_t mx = 0;
+        for (int d = 0; d < nd; ++d) mx += (gd.dsize[d] - 1) * gd.dstride[d][a];
+        for (int i = 0; i < ni; ++i) mx += (gd.isize[i] - 1) * gd.istride[i][a];
+        if (mx >= P->fnum[X[a]]) return false;
+      }
+      if (gd.total >= ((int64_t)1 << 31)) return false;
+      P->gnum[role] = std::max(P->gnum[role], gd.total);
+    }
+    int64_t xs = 1;
+    for (int l = X[nx - 1] + 1; l < N; ++l) xs *= I[l];
+    if (role == 0) {
+      m.u_src = nx == 1 ? SRC_F0 + X[0] : SRC_G0;
+      g.u_ru = r_st; g.u_cu = c_st; g.u_k = k_st; g.Ru = (int32_t)Rk; g.Cu = Cx;
+      x.x_cu = xs;
+    } else {
+      m.v_src = nx == 1 ? SRC_F0 + X[0] : SRC_G1;
+      g.v_rv = r_st; g.v_cv = c_st; g.v_k = k_st; g.Rv = (int32_t)Rk; g.Cv = Cx;
+      x.x_cv = xs;
+    }
+  }
+  int64_t xk = 1;
+  for (int l = k + 1; l < N; ++l) xk *= I[l];
+  x.x_ik = xk;
+  return true;
+}
+
 // Operand tables: M_k[ru * Rv + rv, cu * Cv + cv] = sum U[ru, cu, kap] V[rv, cv, kap]
 // where rows follow A_k's bond modes in order (last fastest) and columns the
 // other physical modes in order (last fastest); see the derivation per mode.
-void setup_modes(fctn_plan_s* P) {
+bool setup_modes(fctn_plan_s* P) {
   const int N = P->N;
   const int64_t* I = P->dims;
   int(*R)[FCTN_MAX_ORDER] = P->R;
@@ -164,7 +297,9 @@ void setup_modes(fctn_plan_s* P) {
     MGen& g = m.mg;
     XView& x = m.xv;
     x.Ik = (int32_t)I[k];
-    if (N == 3) {
+    if (N >= 5) {
+      if (!setup_mode_general(P, k)) return false;
+    } else if (N == 3) {
       const int64_t I1 = I[0], I2 = I[1], I3 = I[2];
       const int64_t R12 = R[0][1], R13 = R[0][2], R23 = R[1][2];
       if (k == 0) {
@@ -225,6 +360,7 @@ void setup_modes(fctn_plan_s* P) {
     P->pnum[0] = I1 * I2 * R13 * R14 * R23 * R24;
     P->pnum[1] = I3 * I4 * R13 * R14 * R23 * R24;
   }
+  return true;
 }
 
 inline int ld_mod(int x, int r) { return x + ((r - x % 64) % 64 + 64) % 64; }
@@ -429,6 +565,7 @@ size_t carve(fctn_plan_s* P, char* base) {
     part_bytes = std::max(part_bytes, (size_t)m.geom.nSplit * m.geom.nTiles * 256 * acc_es);
   }
   for (int p = 0; p < 2; ++p) P->P[p] = (N == 4) ? c.take(P->pnum[p] * es) : nullptr;
+  for (int r = 0; r < 2; ++r) P->Gb[r] = P->gnum[r] > 0 ? c.take(P->gnum[r] * es) : nullptr;
   P->part = c.take(part_bytes);
   P->G = (double*)c.take(smax * smax * sizeof(double));
   P->B = (double*)c.take(imax * smax * sizeof(double));
@@ -445,6 +582,7 @@ size_t carve(fctn_plan_s* P, char* base) {
 
 bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
   memset(P, 0, sizeof(*P));
+  P->gmode = -1;
   P->d = *d;
   P->N = d->order;
   P->prec = d->precision;
@@ -460,7 +598,7 @@ bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
     for (int j = 0; j < P->N; ++j) n *= (j == k) ? P->dims[k] : P->R[k][j];
     P->fnum[k] = n;
   }
-  setup_modes(P);
+  if (!setup_modes(P)) return false;
   // the kernels index X, the factors and the pair tensors with 32-bit offsets
   if (P->numel >= ((int64_t)1 << 31)) return false;
   for (int p = 0; p < 2; ++p)
@@ -490,6 +628,8 @@ bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
 const void* src_ptr(fctn_plan_s* P, int src) {
   if (src == SRC_P12) return P->P[0];
   if (src == SRC_P34) return P->P[1];
+  if (src == SRC_G0) return P->Gb[0];
+  if (src == SRC_G1) return P->Gb[1];
   return P->Aw[src - SRC_F0];
 }
 
@@ -552,7 +692,28 @@ int pair_of_mode(int N, int k) {
   return (k <= 1) ? 1 : 0;
 }
 
+// orders N >= 5: (re)build mode k's materialized operand groups unless they
+// were built for mode k from the same factors
+fctn_status ensure_groups(fctn_plan_s* P, int k) {
+  bool fresh = P->gmode == k;
+  for (int f = 0; f < P->N && fresh; ++f)
+    if (f != k && P->gver[f] != P->fver[f]) fresh = false;
+  if (fresh) return FCTN_OK;
+  const ModeInfo& m = P->mode[k];
+  for (int r = 0; r < 2; ++r) {
+    if (!m.gmat[r]) continue;
+    GroupDesc gd = m.gd[r];
+    for (int a = 0; a < gd.nm; ++a) gd.F[a] = P->Aw[m.gmem[r][a]];
+    FCTN_TIMED(P, FCTN_STAGE_PAIR, 2.0 * gd.total * gd.inner * (gd.nm - 1),
+               (double)gd.total * P->es, launch_group(P->prec, gd, P->Gb[r], P->st));
+  }
+  P->gmode = k;
+  for (int f = 0; f < P->N; ++f) P->gver[f] = P->fver[f];
+  return FCTN_OK;
+}
+
 fctn_status prepare_mode(fctn_plan_s* P, int k) {
+  if (P->N >= 5) return ensure_groups(P, k);
   const int p = pair_of_mode(P->N, k);
   if (p >= 0) return ensure_pair(P, p, P->d.reuse == 0);
   return FCTN_OK;
@@ -618,6 +779,10 @@ fctn_status reconstruct(fctn_plan_s* P, int k, void* Z) {
   const int p = pair_of_mode(P->N, k);
   if (p >= 0) {
     fctn_status s = ensure_pair(P, p, P->d.reuse == 0);
+    if (s != FCTN_OK) return s;
+  }
+  if (P->N >= 5) {
+    fctn_status s = ensure_groups(P, k);
     if (s != FCTN_OK) return s;
   }
   const ModeInfo& m = P->mode[k];

@@ -234,6 +234,55 @@ hipError_t launch_pair(int prec, const PairDesc& pd, void* P, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Group operand (orders N >= 5): one thread per output entry decodes its
+// digits into member offsets, then walks the internal bonds as an odometer,
+// accumulating the product of the members' entries.  The group tensors are
+// small next to X (I_a I_b times a few hundred bond values), so this plain
+// form is HBM- and latency-bound, not a contraction worth MFMA tiles.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) group_k(GroupDesc gd, T* __restrict__ G) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < gd.total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t off[kGroupMaxMembers] = {0, 0, 0, 0, 0, 0};
+    int64_t rem = e;
+    for (int d = gd.nd - 1; d >= 0; --d) {
+      const int64_t q = rem % gd.dsize[d];
+      rem /= gd.dsize[d];
+      for (int f = 0; f < gd.nm; ++f) off[f] += q * gd.dstride[d][f];
+    }
+    int64_t idx[kGroupMaxDigits];
+    for (int i = 0; i < gd.ni; ++i) idx[i] = 0;
+    T acc = T(0);
+    for (int64_t t = 0; t < gd.inner; ++t) {
+      T prod = T(1);
+      for (int f = 0; f < gd.nm; ++f) prod *= ((const T*)gd.F[f])[off[f]];
+      acc += prod;
+      // next internal bond value (last digit fastest), moving the offsets along
+      for (int i = gd.ni - 1; i >= 0; --i) {
+        if (++idx[i] < gd.isize[i]) {
+          for (int f = 0; f < gd.nm; ++f) off[f] += gd.istride[i][f];
+          break;
+        }
+        for (int f = 0; f < gd.nm; ++f) off[f] -= (gd.isize[i] - 1) * gd.istride[i][f];
+        idx[i] = 0;
+      }
+    }
+    G[e] = acc;
+  }
+}
+
+hipError_t launch_group(int prec, const GroupDesc& gd, void* G, hipStream_t st) {
+  if (gd.total == 0) return hipSuccess;
+  const int nb = (int)(cdiv(gd.total, 256) < 8192 ? cdiv(gd.total, 256) : 8192);
+  if (prec == P_F64)
+    group_k<double><<<nb, 256, 0, st>>>(gd, (double*)G);
+  else
+    group_k<float><<<nb, 256, 0, st>>>(gd, (float*)G);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // eq. 10 as a select: X on Omega already equals Y, so only X, Z and the mask
 // bits are read.  Per-block float64 partials: ||X+ - X||^2, ||X||^2,
 // ||X+ - Z||^2.  16-byte vector accesses; a fixed grid keeps the partial

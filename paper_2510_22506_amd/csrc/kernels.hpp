@@ -83,6 +83,23 @@ struct PairDesc {
 // precision codes shared with the C ABI
 enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
 
+// Sub-network operand for orders N >= 5: the contraction of a group of
+// consecutive factors over the bonds inside the group,
+//   G[d_0, .., d_{nd-1}] = sum over the internal bonds of prod_f F_f[off_f],
+// where output digit d (last fastest) adds d * dstride[d][f] to member f's
+// offset and internal digit i adds i * istride[i][f].
+constexpr int kGroupMaxMembers = 6;
+constexpr int kGroupMaxDigits = 16;
+struct GroupDesc {
+  const void* F[kGroupMaxMembers];
+  int64_t dsize[kGroupMaxDigits];
+  int64_t dstride[kGroupMaxDigits][kGroupMaxMembers];
+  int64_t isize[kGroupMaxDigits];
+  int64_t istride[kGroupMaxDigits][kGroupMaxMembers];
+  int32_t nm, nd, ni;
+  int64_t total, inner;   // output entries, terms per entry
+};
+
 // one factor's shapes before and after a rank growth (last mode fastest);
 // bit j of zero_modes: new indices along mode j give zero entries
 struct RegrowDesc {
@@ -114,6 +131,7 @@ hipError_t launch_cast_factor(int prec, const double* A64, void* Aw, void* Au, i
 hipError_t launch_build_basis(double* Q, double* Qt, double* lam_col, int32_t n, double delta,
                               hipStream_t st);
 hipError_t launch_pair(int prec, const PairDesc& pd, void* P, hipStream_t st);
+hipError_t launch_group(int prec, const GroupDesc& gd, void* G, hipStream_t st);
 hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView& xv,
                            const GramGeom& g, void* part, hipStream_t st);
 hipError_t launch_reduce_gb(int prec, const GramGeom& g, const void* part, const double* A64,

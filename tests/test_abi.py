@@ -53,8 +53,9 @@ def test_workspace_bytes_and_validation(F):
         assert F.fctn_workspace_bytes(b) == 0
     assert F.fctn_workspace_bytes(F.make_desc((32, 32, 8), (3, 3, 3), precision="f64",
                                               extrapolation=(0.5, 0.5))) == n
-    # valid for the method, outside this build: N = 5, rank products above 192
-    assert F.fctn_workspace_bytes(F.make_desc((3,) * 5, (2,) * 10)) == 0
+    # valid for the method, outside this build: N = 7, N = 2, rank products above 192
+    assert F.fctn_workspace_bytes(F.make_desc((3,) * 7, (2,) * 21)) == 0
+    assert F.fctn_workspace_bytes(F.make_desc((5, 4), (2,))) == 0
     assert F.fctn_workspace_bytes(F.make_desc((8, 8, 8), (16, 16, 2))) == 0
 
 
@@ -71,6 +72,10 @@ def test_mode_sizes(F):
     assert [F.fctn_mode_sizes(d, k) for k in range(4)] == [(192, 144), (192, 176), (27, 3), (192, 50)]
     with pytest.raises(F.FctnError):
         F.fctn_mode_sizes(d, 4)
+    d5 = F.make_desc((6, 5, 4, 3, 2), (2, 3, 1, 2, 3, 1, 2, 2, 1, 3))
+    # s_k = product of the bonds at k, e.g. s_1 = R12 R13 R14 R15 = 2 * 3 * 1 * 2
+    assert [F.fctn_mode_sizes(d5, k) for k in range(5)] == \
+        [(12, 6), (12, 5), (18, 4), (6, 3), (12, 2)]
 
 
 def test_plan_rejects_bad_arguments_without_touching_the_device(F):
@@ -97,6 +102,12 @@ def test_every_small_shape_is_supported(F):
     for dims in [(1, 1, 1, 1), (2, 3, 1, 2), (13, 11, 3, 7), (5, 3, 3, 2)]:
         if F.fctn_workspace_bytes(F.make_desc(dims, (2,) * 6, precision="f32")) == 0:
             bad.append(dims)
+    # orders 5 and 6 (operand groups built per mode)
+    for dims in [(1, 1, 1, 1, 1), (3, 4, 2, 5, 3), (9, 7, 3, 4, 5), (2, 3, 2, 2, 3, 2)]:
+        ranks = (2,) * (len(dims) * (len(dims) - 1) // 2)
+        for p in ("f64", "f32", "bf16x3"):
+            if F.fctn_workspace_bytes(F.make_desc(dims, ranks, precision=p)) == 0:
+                bad.append((dims, p))
     assert not bad
 
 
