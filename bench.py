@@ -25,7 +25,7 @@ workload.
 Other workloads (--workload): c1 low-rank 32x32x8 (float64), c2 color image
 256x256x3, c4 multispectral 512x512x31, c5 new-video 500x550x3x24, c6
 multi-temporal 300x300x4x5 (with the asymmetric extrapolation, as the paper
-runs its multi-temporal images).
+runs its multi-temporal images), c7 low-rank order-5 32x32x32x32x8.
 """
 
 import argparse
@@ -49,8 +49,10 @@ WORKLOADS = {
     "c1": ("c1", None, "low-rank order-3 32x32x8, ranks (3,3,3), SR 0.3"),
     "c5": ("c5", None, "new-video-shaped order-4 500x550x3x24, ranks (8,3,8,3,8,3), SR 0.05"),
     "c6": ("c6", None, "multi-temporal order-4 300x300x4x5, ranks (8,3,4,3,4,3), SR 0.05"),
+    "c7": ("c7", None, "low-rank order-5 32x32x32x32x8, all ten ranks 3, SR 0.1"),
 }
-DEFAULT_PREC = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f32", "c5": "f32", "c6": "f32"}
+DEFAULT_PREC = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f32", "c5": "f32", "c6": "f32",
+                "c7": "f32"}
 # the paper runs its multi-temporal images with the asymmetric extrapolation
 # (alpha = beta = 0.5, Section 4.2) and its videos without
 DEFAULT_EXTRAP = {"c6": (0.5, 0.5)}

@@ -217,46 +217,56 @@ bool setup_mode_general(fctn_plan_s* P, int k) {
         gd.dsize[nd] = size;
         return nd++;
       };
+      int64_t mx[kGroupMaxMembers] = {0, 0, 0, 0, 0, 0};   // largest offset per member
+      auto put = [&](int d, int a, int64_t st) {
+        gd.dmem[d] = a;
+        gd.dstr[d] = (int32_t)st;
+        mx[a] += (gd.dsize[d] - 1) * st;
+      };
       for (int a = 0; a < nx; ++a) {          // physical indices
         const int d = digit(I[X[a]]);
         if (d < 0) return false;
-        gd.dstride[d][a] = fstride(P, X[a], X[a]);
+        put(d, a, fstride(P, X[a], X[a]));
       }
       for (int a = 0; a < nx; ++a) {          // bonds to k
         const int d = digit(R[X[a]][k]);
         if (d < 0) return false;
-        gd.dstride[d][a] = fstride(P, X[a], k);
+        put(d, a, fstride(P, X[a], k));
       }
       for (int a = 0; a < ns; ++a)            // cross bonds, s-major
         for (int b = 0; b < nt; ++b) {
           const int d = digit(R[S[a]][T[b]]);
           if (d < 0) return false;
-          if (role == 0) gd.dstride[d][a] = fstride(P, S[a], T[b]);
-          else gd.dstride[d][b] = fstride(P, T[b], S[a]);
+          if (role == 0) put(d, a, fstride(P, S[a], T[b]));
+          else put(d, b, fstride(P, T[b], S[a]));
         }
       gd.nd = nd;
       int ni = 0;
-      gd.inner = 1;
+      int64_t inner = 1;
       for (int a = 0; a < nx; ++a)            // bonds inside the group
         for (int b = a + 1; b < nx; ++b) {
           if (ni >= kGroupMaxDigits) return false;
-          gd.isize[ni] = R[X[a]][X[b]];
-          gd.istride[ni][a] = fstride(P, X[a], X[b]);
-          gd.istride[ni][b] = fstride(P, X[b], X[a]);
-          gd.inner *= gd.isize[ni];
+          const int64_t sz = R[X[a]][X[b]];
+          gd.isize[ni] = (int32_t)sz;
+          gd.imem0[ni] = a;
+          gd.istr0[ni] = (int32_t)fstride(P, X[a], X[b]);
+          gd.imem1[ni] = b;
+          gd.istr1[ni] = (int32_t)fstride(P, X[b], X[a]);
+          mx[a] += (sz - 1) * gd.istr0[ni];
+          mx[b] += (sz - 1) * gd.istr1[ni];
+          inner *= sz;
           ++ni;
         }
       gd.ni = ni;
-      gd.total = Cx * Rk * Kc;
-      // every offset the kernel forms stays inside its member factor
-      for (int a = 0; a < nx; ++a) {
-        int64_t mx = 0;
-        for (int d = 0; d < nd; ++d) mx += (gd.dsize[d] - 1) * gd.dstride[d][a];
-        for (int i = 0; i < ni; ++i) mx += (gd.isize[i] - 1) * gd.istride[i][a];
-        if (mx >= P->fnum[X[a]]) return false;
-      }
-      if (gd.total >= ((int64_t)1 << 31)) return false;
-      P->gnum[role] = std::max(P->gnum[role], gd.total);
+      const int64_t total = Cx * Rk * Kc;
+      // entry count and every offset the kernel forms fit 31 bits and stay
+      // inside the member factors
+      if (total >= ((int64_t)1 << 31) || inner > kGroupMaxInner) return false;
+      for (int a = 0; a < nx; ++a)
+        if (mx[a] >= P->fnum[X[a]]) return false;
+      gd.total = (int32_t)total;
+      gd.inner = (int32_t)inner;
+      P->gnum[role] = std::max(P->gnum[role], total);
     }
     int64_t xs = 1;
     for (int l = X[nx - 1] + 1; l < N; ++l) xs *= I[l];

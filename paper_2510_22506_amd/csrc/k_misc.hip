@@ -242,31 +242,43 @@ hipError_t launch_pair(int prec, const PairDesc& pd, void* P, hipStream_t st) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) group_k(GroupDesc gd, T* __restrict__ G) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < gd.total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t off[kGroupMaxMembers] = {0, 0, 0, 0, 0, 0};
-    int64_t rem = e;
-    for (int d = gd.nd - 1; d >= 0; --d) {
-      const int64_t q = rem % gd.dsize[d];
-      rem /= gd.dsize[d];
-      for (int f = 0; f < gd.nm; ++f) off[f] += q * gd.dstride[d][f];
-    }
-    int64_t idx[kGroupMaxDigits];
-    for (int i = 0; i < gd.ni; ++i) idx[i] = 0;
-    T acc = T(0);
-    for (int64_t t = 0; t < gd.inner; ++t) {
-      T prod = T(1);
-      for (int f = 0; f < gd.nm; ++f) prod *= ((const T*)gd.F[f])[off[f]];
-      acc += prod;
-      // next internal bond value (last digit fastest), moving the offsets along
-      for (int i = gd.ni - 1; i >= 0; --i) {
-        if (++idx[i] < gd.isize[i]) {
-          for (int f = 0; f < gd.nm; ++f) off[f] += gd.istride[i][f];
-          break;
-        }
-        for (int f = 0; f < gd.nm; ++f) off[f] -= (gd.isize[i] - 1) * gd.istride[i][f];
-        idx[i] = 0;
+  // the member offsets of every internal bond value, once per workgroup
+  __shared__ int32_t tab[kGroupMaxInner * kGroupMaxMembers];
+  for (int t = threadIdx.x; t < gd.inner; t += blockDim.x) {
+    int32_t o[kGroupMaxMembers] = {0, 0, 0, 0, 0, 0};
+    uint32_t rem = (uint32_t)t;
+    for (int i = gd.ni - 1; i >= 0; --i) {
+      const uint32_t q = rem % (uint32_t)gd.isize[i];
+      rem /= (uint32_t)gd.isize[i];
+#pragma unroll
+      for (int f = 0; f < kGroupMaxMembers; ++f) {
+        o[f] += gd.imem0[i] == f ? (int32_t)q * gd.istr0[i] : 0;
+        o[f] += gd.imem1[i] == f ? (int32_t)q * gd.istr1[i] : 0;
       }
+    }
+#pragma unroll
+    for (int f = 0; f < kGroupMaxMembers; ++f) tab[t * kGroupMaxMembers + f] = o[f];
+  }
+  __syncthreads();
+  for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < gd.total;
+       e += gridDim.x * blockDim.x) {
+    int32_t off[kGroupMaxMembers] = {0, 0, 0, 0, 0, 0};
+    uint32_t rem = (uint32_t)e;
+    for (int d = gd.nd - 1; d >= 0; --d) {
+      const uint32_t sz = (uint32_t)gd.dsize[d];
+      const uint32_t q = rem % sz;
+      rem /= sz;
+      const int32_t add = (int32_t)q * gd.dstr[d];
+#pragma unroll
+      for (int f = 0; f < kGroupMaxMembers; ++f) off[f] += gd.dmem[d] == f ? add : 0;
+    }
+    T acc = T(0);
+    for (int32_t t = 0; t < gd.inner; ++t) {
+      T prod = T(1);
+#pragma unroll
+      for (int f = 0; f < kGroupMaxMembers; ++f)
+        if (f < gd.nm) prod *= ((const T*)gd.F[f])[off[f] + tab[t * kGroupMaxMembers + f]];
+      acc += prod;
     }
     G[e] = acc;
   }

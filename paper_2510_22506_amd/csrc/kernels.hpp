@@ -86,18 +86,20 @@ enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
 // Sub-network operand for orders N >= 5: the contraction of a group of
 // consecutive factors over the bonds inside the group,
 //   G[d_0, .., d_{nd-1}] = sum over the internal bonds of prod_f F_f[off_f],
-// where output digit d (last fastest) adds d * dstride[d][f] to member f's
-// offset and internal digit i adds i * istride[i][f].
+// where output digit d (last fastest) adds d * dstr[d] to member dmem[d]'s
+// offset and internal digit i adds i * istr0[i] to member imem0[i] and
+// i * istr1[i] to member imem1[i] (a bond joins two members).  All offsets
+// and the entry count fit 31 bits (checked at plan time).
 constexpr int kGroupMaxMembers = 6;
 constexpr int kGroupMaxDigits = 16;
+constexpr int kGroupMaxInner = 1024;   // internal bond values per entry
 struct GroupDesc {
   const void* F[kGroupMaxMembers];
-  int64_t dsize[kGroupMaxDigits];
-  int64_t dstride[kGroupMaxDigits][kGroupMaxMembers];
-  int64_t isize[kGroupMaxDigits];
-  int64_t istride[kGroupMaxDigits][kGroupMaxMembers];
+  int32_t dsize[kGroupMaxDigits], dmem[kGroupMaxDigits], dstr[kGroupMaxDigits];
+  int32_t isize[kGroupMaxDigits], imem0[kGroupMaxDigits], istr0[kGroupMaxDigits];
+  int32_t imem1[kGroupMaxDigits], istr1[kGroupMaxDigits];
   int32_t nm, nd, ni;
-  int64_t total, inner;   // output entries, terms per entry
+  int32_t total, inner;   // output entries, terms per entry
 };
 
 // one factor's shapes before and after a rank growth (last mode fastest);

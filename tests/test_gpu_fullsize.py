@@ -3,7 +3,8 @@ times (reuse on, alternating order): two PAM sweeps of the image-shaped
 256x256x3, video-shaped 144x176x3x50 and multispectral-shaped 512x512x31
 configurations, and of the paper's second workload set (a 500x550x3x24 video
 and a 300x300x4x5 multi-temporal image, run with the asymmetric extrapolation
-at alpha = beta = 0.5 as the paper runs it), against the FP64 oracle on the same
+at alpha = beta = 0.5 as the paper runs it), and an order-5 32x32x32x32x8
+low-rank tensor, against the FP64 oracle on the same
 seeded inputs (the oracle finishes the two sweeps in seconds, the 500x550x3x24
 case in under a minute; its result is shared by the two precisions).  float32 to 1e-5 relative, split
 bf16 to 2e-4, observed entries bit for bit, and the per-sweep objective and
@@ -43,6 +44,7 @@ def _oracle(name, ext):
     ("c4", "f32", 1e-5, None), ("c4", "bf16x3", 2e-4, None),
     ("c5", "f32", 1e-5, None), ("c5", "bf16x3", 2e-4, None),
     ("c6", "f32", 1e-5, (0.5, 0.5)), ("c6", "bf16x3", 2e-4, (0.5, 0.5)),
+    ("c7", "f32", 1e-5, None),
 ])
 def test_full_size_sweeps(name, prec, tol, ext):
     from paper_2510_22506_amd import Plan

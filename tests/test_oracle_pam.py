@@ -205,6 +205,9 @@ def test_generators_shapes_and_ranges():
     assert [a.shape for a in m.A0] == factor_shapes_of(m.dims, m.ranks)
     # dates differ (blobs drift and change amplitude between acquisitions)
     assert np.abs(m.truth[..., 0] - m.truth[..., 4]).max() > 1e-3
+    o5 = make_problem("c7", seed=5, dims=(4, 5, 3, 4, 2))
+    assert o5.Y.shape == (4, 5, 3, 4, 2) and o5.truth.min() == 0.0 and o5.truth.max() == 1.0
+    assert [a.shape for a in o5.A0] == factor_shapes_of(o5.dims, o5.ranks)
     v = make_problem("c5", seed=4, dims=(20, 22, 3, 4))
     assert v.Y.shape == (20, 22, 3, 4) and abs(v.mask.mean() - 0.05) < 0.03
 

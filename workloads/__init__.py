@@ -10,6 +10,6 @@ or X updates) and imports neither the oracle nor the GPU library.
 
 from .generators import (  # noqa: F401
     CONFIGS, Problem, make_problem, init_factors, bernoulli_mask,
-    factor_shapes_of, lowrank_order3, color_image, video, multispectral,
+    factor_shapes_of, lowrank_order3, lowrank_order5, color_image, video, multispectral,
     multitemporal, serving_requests, rank_growth_draws,
 )

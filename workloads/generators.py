@@ -85,6 +85,23 @@ def lowrank_order3(rng, dims, rank=3, taps=5):
     return (x - x.min()) / (x.max() - x.min())
 
 
+def lowrank_order5(rng, dims, rank=3, taps=5):
+    """Order-5 low-FCTN-rank tensor built like lowrank_order3: Gaussian factors
+    with all ten bonds `rank`, each circularly box-filtered along its physical
+    mode, combined by the FCTN sum over the ten bonds (one einsum, data
+    synthesis only) and min-max scaled to [0, 1]."""
+    shapes = factor_shapes_of(dims, (rank,) * 10)
+    fs = []
+    for k, s in enumerate(shapes):
+        a = rng.standard_normal(s)
+        acc = np.zeros_like(a)
+        for d in range(-(taps // 2), taps // 2 + 1):
+            acc += np.roll(a, d, axis=k)
+        fs.append(acc / taps)
+    x = np.einsum("iABCD,AjEFG,BEkHI,CFHlJ,DGIJm->ijklm", *fs, optimize="greedy")
+    return (x - x.min()) / (x.max() - x.min())
+
+
 def color_image(rng, H, W, n_sines=8, n_ellipses=6):
     """H x W x 3 color image in [0, 1]: per channel 0.5 plus n_sines random 2-D
     sinusoids (amplitude U(0.02, 0.1), frequency U(0.5, 8) cycles per image
@@ -231,6 +248,8 @@ CONFIGS = {
     # image (300 x 300 x 4 bands x 5 dates)
     "c5": ("video", (500, 550, 3, 24), (8, 3, 8, 3, 8, 3), 0.05, 100, "f32"),
     "c6": ("multitemporal", (300, 300, 4, 5), (8, 3, 4, 3, 4, 3), 0.05, 100, "f32"),
+    # Table 2's N-th order case at N = 5 (the paper runs no order-5 data)
+    "c7": ("lowrank5", (32, 32, 32, 32, 8), (3,) * 10, 0.1, 50, "f32"),
 }
 
 
@@ -243,6 +262,8 @@ def _truth(kind, rng, dims):
         return video(rng, dims[0], dims[1], dims[3])
     if kind == "spectral":
         return multispectral(rng, dims[0], dims[1], dims[2])
+    if kind == "lowrank5":
+        return lowrank_order5(rng, dims)
     if kind == "multitemporal":
         return multitemporal(rng, dims[0], dims[1], dims[2], dims[3])
     raise ValueError(kind)
