@@ -65,7 +65,7 @@ typedef struct fctn_plan_s* fctn_plan_t;
 
 /* Problem descriptor: the inputs of Algorithms 1-2 apart from Y and Omega. */
 typedef struct {
-  int32_t order;                    /* N; this build runs N = 3 and N = 4    */
+  int32_t order;                    /* N; this build runs N = 3 .. 6         */
   int64_t dims[FCTN_MAX_ORDER];     /* I_1 .. I_N, each >= 1                 */
   int32_t ranks[FCTN_MAX_BONDS];    /* r_FCTN in the order above, each >= 1  */
   double lambda[FCTN_MAX_ORDER];    /* lambda_k >= 0 (eq. model_1)           */
@@ -187,7 +187,8 @@ fctn_status fctn_get_factor(fctn_plan_t plan, int32_t k, double* dst_dev);
  * rho A_k(k), both float64 row-major.  The s_k index is the bond multi-index
  * of A_k in its mode order with the last bond fastest; the columns of M_k
  * and X_(k) are the other physical indices, last fastest.  For N = 4 the
- * needed pair tensor is (re)built first. */
+ * needed pair tensor is (re)built first; for N = 5, 6 the mode's operand
+ * groups (contractions of consecutive factors) are. */
 fctn_status fctn_step_gram_rhs(fctn_plan_t plan, int32_t k, double* G_dev,
                                double* B_dev);
 
@@ -282,7 +283,7 @@ fctn_status fctn_server_destroy(fctn_server_t server);
 /* ---- per-kernel timing ---------------------------------------------------
  * Stages, one per kernel of a sweep: */
 enum {
-  FCTN_STAGE_PAIR = 0,        /* pair tensor of the reuse mechanism (N = 4)  */
+  FCTN_STAGE_PAIR = 0,        /* pair tensor (N = 4) or operand groups (N >= 5) */
   FCTN_STAGE_GRAM_RHS = 1,    /* fused M_k generation + Gram + RHS (eq. 5)   */
   FCTN_STAGE_REDUCE = 2,      /* float64 split-K reduction (+ rho A_k)        */
   FCTN_STAGE_SOLVE = 3,       /* per-class Cholesky solves (eq. 5-8)          */
