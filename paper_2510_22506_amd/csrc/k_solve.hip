@@ -295,16 +295,29 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
     __syncthreads();
     FCTN_SOLVE_MARK(24 + 2 * p);
     if (wave == 0) {
+      // lane q (and q + 32 for the second right-hand side) carries z_q; step j
+      // takes x_j = z_j / L_jj from lane j and removes L[j][q] x_j.  The
+      // multipliers L[j][q] are read from LDS eight steps ahead, and each lane
+      // scales its own z by its own 1 / L_qq, so the serial chain holds only
+      // the two readlanes and a multiply-add.
       const int q = lane & 31, v = lane >> 5;
       double z = q < np ? rhs[v * LDP + p0 + q] - tpart[v * 32 + q] : 0.0;
+      const double rd = rdiag[p0 + q];
 #pragma unroll
-      for (int j = 31; j >= 0; --j) {
-        if (j < np) {
-          const double za = bcast_lane(z, j), zb = bcast_lane(z, 32 + j);
-          const double xj = (v ? zb : za) * rdiag[p0 + j];
-          const double raw = smem[j * 33 + q];
-          const double l = q < j ? raw : 0.0;
-          z = q == j ? xj : z - l * xj;
+      for (int j8 = 3; j8 >= 0; --j8) {
+        double l8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) l8[u] = smem[(8 * j8 + u) * 33 + q];
+#pragma unroll
+        for (int u = 7; u >= 0; --u) {
+          const int j = 8 * j8 + u;
+          if (j < np) {
+            const double w = z * rd;
+            const double xa = bcast_lane(w, j), xb = bcast_lane(w, 32 + j);
+            const double xj = v ? xb : xa;
+            const double l = q < j ? l8[u] : 0.0;
+            z = q == j ? xj : z - l * xj;
+          }
         }
         __builtin_amdgcn_sched_barrier(0);
       }
