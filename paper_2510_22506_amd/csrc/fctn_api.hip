@@ -490,17 +490,15 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
     }
   }
   g.xrows = xmax;
-  if (!bf) {
-    g.ldm = ld_pad(g.sp);
-    g.ldx = ld_pad(std::max(xmax, 16));
-  }
-  // bf16 tiles are [row][column] with a row stride of tcolp + 8 bf16 values
+  // M and X tiles are [row][column]; bf16 rows are tcolp + 8 bf16 values long,
+  // float32/float64 rows tcolp + 16 bytes (16-byte aligned after the slabs)
   auto gram_lds = [&](const TileGeom& tg) {
     if (bf)
       return (size_t)(tg.u_len + tg.v_len) * es + table_bytes(tg, true) +
              (size_t)(g.sp + xmax) * (tg.tcolp + 8) * 2 * nbf;
-    return (size_t)(tg.u_len + tg.v_len + (size_t)tg.tcolp * (g.ldm + g.ldx)) * es +
-           table_bytes(tg, true);
+    const size_t slabs = (table_bytes(tg, true) + (size_t)(tg.u_len + tg.v_len) * es + 15) &
+                         ~(size_t)15;
+    return slabs + (size_t)(g.sp + xmax) * (tg.tcolp + 16 / es) * es;
   };
   // consumer MFMA time per tile in fp32-16x16x4 units (a bf16 16x16x32 issue
   // takes about half as long and covers 8 times the k range)
@@ -508,11 +506,15 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
     if (bf) return (double)g.nTiles * (tg.tcolp / 32) * (nbf == 2 ? 3 : 1) * 0.5;
     return (double)g.nTiles * (tg.tcolp / 4);
   };
-  if (!choose_tile(m.mg, g.nGroups, bf ? 32 : 4, gram_work, gram_lds, &g.tg)) return false;
+  // column tiles in whole 16-byte reads per lane group: 4 (16 / es) columns
+  if (!choose_tile(m.mg, g.nGroups, bf ? 32 : 64 / (int)es, gram_work, gram_lds, &g.tg))
+    return false;
   if (bf) {
     g.ldm = g.tg.tcolp + 8;
-    g.ldx = g.ldm;
+  } else {
+    g.ldm = g.tg.tcolp + 16 / (int)es;
   }
+  g.ldx = g.ldm;
   g.lds_bytes = gram_lds(g.tg);
   int64_t ns = std::max<int64_t>(1, kTargetGramWGs / g.nGroups);
   ns = std::min<int64_t>(ns, g.tg.nColTiles);

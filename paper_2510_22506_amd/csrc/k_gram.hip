@@ -235,6 +235,8 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
                                                            XView xv, GramGeom g,
                                                            T* __restrict__ part) {
   typedef Mfma<T> MM;
+  constexpr int VW = 16 / (int)sizeof(T);   // columns per 16-byte LDS read
+  typedef T vT __attribute__((ext_vector_type(VW)));
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileGeom& tg = g.tg;
   SlabRow* ptab = (SlabRow*)smem_raw;
@@ -242,8 +244,11 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
   SlabRow* ctab = qtab + tg.Qp;
   T* Us = (T*)(ctab + tg.tcolp);
   T* Vs = Us + tg.u_len;
-  T* Ms = Vs + tg.v_len;                        // [tcolp][ldm]  rows of M fastest
-  T* Xs = Ms + (int64_t)tg.tcolp * g.ldm;       // [tcolp][ldx]  rows of X_(k) fastest
+  // [row][column] tiles, columns contiguous, row strides ldm = ldx = tcolp +
+  // 16 bytes: one 16-byte read per lane covers VW columns, i.e. VW MFMAs
+  const int mso = ((int)((unsigned char*)(Vs + tg.v_len) - smem_raw) + 15) & ~15;
+  T* Ms = (T*)(smem_raw + mso);                                         // [sp][ldm]
+  T* Xs = Ms + (int64_t)g.sp * g.ldm;                                   // [xrows][ldx]
   const T* U = (const T*)mg.U;
   const T* V = (const T*)mg.V;
 
@@ -288,12 +293,11 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
     tdesc[j] = (fx ? 1 : 0) | (bi << 1) | (bj << 11);
   }
 
-  build_tables(mg, tg, &xv, 1, g.ldm, ptab, qtab, ctab, tid, kGramThreads);
+  build_tables(mg, tg, &xv, g.ldm, 1, ptab, qtab, ctab, tid, kGramThreads);
   // rows of M beyond s and columns beyond the tile (in M and X) stay zero for
   // the whole launch: uninitialized LDS could hold NaN patterns, and NaN * 0
   // would poison the products
-  for (int e = tid; e < tg.tcolp * g.ldm; e += kGramThreads) Ms[e] = T(0);
-  for (int e = tid; e < tg.tcolp * g.ldx; e += kGramThreads) Xs[e] = T(0);
+  for (int e = tid; e < (g.sp + g.xrows) * g.ldm; e += kGramThreads) Ms[e] = T(0);
   __syncthreads();
 
   const int64_t ct0 = (int64_t)split * g.colTilesPerSplit;
@@ -321,13 +325,13 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
           const SlabRow cr = ctab[c];
           const bool okc = cr.cl < lim_u && cr.map < lim_v;
           for (int r = l; r < xrows; r += xl)
-            Xs[c * ldx + r] = (okc && r < xlim) ? xb[cr.off + (int64_t)r * xv.x_ik] : T(0);
+            Xs[r * ldx + c] = (okc && r < xlim) ? xb[cr.off + (int64_t)r * xv.x_ik] : T(0);
         }
       } else {
         for (int e = tid; e < tg.tcol * xrows; e += kGramThreads) {
           const int r = e / tg.tcol, c = e - r * tg.tcol;
           const SlabRow cr = ctab[c];
-          Xs[c * ldx + r] = (cr.cl < lim_u && cr.map < lim_v && r < xlim)
+          Xs[r * ldx + c] = (cr.cl < lim_u && cr.map < lim_v && r < xlim)
                                 ? xb[cr.off + (int64_t)r * xv.x_ik] : T(0);
         }
       }
@@ -339,18 +343,24 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
     FCTN_GRAM_MARK(3);
     __syncthreads();
     FCTN_GRAM_MARK(4);
-    const int kr = lane >> 4;
+    // lane group kr reads columns kk + VW kr .. + VW - 1 of its row in one
+    // 16-byte load and feeds them to VW MFMAs; MFMA m therefore sums the
+    // columns {kk + VW kr + m}, and the VW MFMAs cover kk .. kk + 4 VW - 1
+    // once, in the same order for both operands
+    const int kof = (lane >> 4) * VW;
 #pragma unroll
     for (int j = 0; j < kTPW; ++j) {
       if (valid[j]) {
         const int d = tdesc[j];
-        const T* Ab = (d & 1) ? Xs : Ms;
-        const int lda = (d & 1) ? ldx : ldm;
-        const int ao = ((d >> 1) & 1023) * 16 + (lane & 15), bo = (d >> 11) * 16 + (lane & 15);
-        for (int kk = 0; kk < tg.tcolp; kk += MM::kStep) {
-          const T a = Ab[(kk + kr) * lda + ao];
-          const T b = Ms[(kk + kr) * ldm + bo];
-          acc[j] = MM::mma(a, b, acc[j]);
+        const T* Ab = ((d & 1) ? Xs + (((d >> 1) & 1023) * 16 + (lane & 15)) * ldx
+                               : Ms + (((d >> 1) & 1023) * 16 + (lane & 15)) * ldm) + kof;
+        const T* Bb = Ms + ((d >> 11) * 16 + (lane & 15)) * ldm + kof;
+#pragma unroll 1
+        for (int kk = 0; kk < tg.tcolp; kk += 4 * VW) {
+          const vT a = *(const vT*)(Ab + kk);
+          const vT b = *(const vT*)(Bb + kk);
+#pragma unroll
+          for (int m = 0; m < VW; ++m) acc[j] = MM::mma(a[m], b[m], acc[j]);
         }
       }
     }
