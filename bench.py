@@ -132,7 +132,9 @@ def serving(args):
     {10,25,50}, sampling rates {0.05,0.1,0.2}) through the continuous-batching
     server.  Poisson arrivals at `serve_rate` in the bf16 served form (split
     bf16), then saturation runs (every request at t = 0) of the same mix in
-    split bf16 and in float32, with per-request PSNR of the two forms."""
+    split bf16, plain bf16 and float32, with per-request PSNR against float32
+    (plain bf16 misses the 1e-3 bound against the oracle, so it is reported
+    beside the served form, not as it)."""
     import numpy as np
     import torch
     from paper_2510_22506_amd import Server, serve
@@ -162,27 +164,31 @@ def serving(args):
         poisson = serve.run(srv, requests("bf16x3", range(len(spec))),
                             [q["arrival"] for q in spec])
         sat = {prec: serve.run(srv, requests(prec, range(len(spec))))
-               for prec in ("bf16x3", "f32")}
+               for prec in ("bf16x3", "bf16", "f32")}
     finally:
         srv.close()
-    dpsnr = []
-    for i, p in enumerate(probs):
-        a = psnr(p.truth, sat["bf16x3"]["done"][i][1].cpu().numpy())
-        b = psnr(p.truth, sat["f32"]["done"][i][1].cpu().numpy())
-        dpsnr.append(a - b)
-    dpsnr = np.abs(np.array(dpsnr))
+
+    def dpsnr_of(form):
+        d = [psnr(p.truth, sat[form]["done"][i][1].cpu().numpy()) -
+             psnr(p.truth, sat["f32"]["done"][i][1].cpu().numpy()) for i, p in enumerate(probs)]
+        return np.abs(np.array(d))
+    dpsnr = dpsnr_of("bf16x3")
+    dpsnr1 = dpsnr_of("bf16")
     out = {"requests": len(spec), "sweeps_per_request": args.serve_sweeps,
            "arrival_rate_per_s": args.serve_rate, "form": "bf16x3",
            "poisson": serve.summarize(poisson),
            "saturation": {k: serve.summarize(v) for k, v in sat.items()},
            "psnr_bf16x3_vs_f32_abs_db": {"mean": float(dpsnr.mean()),
                                          "max": float(dpsnr.max())},
+           "psnr_bf16_vs_f32_abs_db": {"mean": float(dpsnr1.mean()),
+                                       "max": float(dpsnr1.max())},
            "server": {"arena_bytes": arena, "budget_bytes": int(args.serve_budget),
                       "streams": args.serve_streams, "max_active": args.serve_active,
                       "depth": args.serve_depth}}
-    out["saturation_speedup_bf16x3_over_f32"] = (
-        out["saturation"]["bf16x3"]["completions_per_s"] /
-        out["saturation"]["f32"]["completions_per_s"])
+    for form in ("bf16x3", "bf16"):
+        out[f"saturation_speedup_{form}_over_f32"] = (
+            out["saturation"][form]["completions_per_s"] /
+            out["saturation"]["f32"]["completions_per_s"])
     return out
 
 
