@@ -526,7 +526,9 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
   r.sp = g.sp;
   r.Ik = g.Ik;
   r.ip = g.ip;
-  const int lda = ld_mod(r.sp, 16);
+  // rows of the staged A_k(k) and of the M tile 16 bytes apart modulo 256:
+  // the 16 lanes of one 16-byte read hit distinct banks
+  const int lda = ld_mod(r.sp, 4);
   // A_k(k) in LDS only when small: a large copy would leave room for one
   // workgroup per CU (it is read through the cache otherwise)
   const bool stage_a = (size_t)r.ip * lda * es <= 24 * 1024;
@@ -534,7 +536,7 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
   auto rec_lds = [&](const TileGeom& tg) {
     const int ldm = ld_mod(std::max(r.sp, 4), 4);
     return (size_t)(tg.u_len + tg.v_len + (size_t)pad16(tg.tcolp) * ldm + (size_t)r.ip * r.lda) *
-               es + table_bytes(tg, false);
+               es + table_bytes(tg, false) + 16;
   };
   auto rec_work = [&](const TileGeom& tg) {
     return (double)(r.ip / 16) * (pad16(tg.tcolp) / 16) * (r.sp / 4);

@@ -650,13 +650,16 @@ __global__ void __launch_bounds__(kRecThreads) reconstruct_k(MGen mg, const T* _
                                                              T* __restrict__ Z, XView xv,
                                                              RecGeom g) {
   typedef Mfma<T> MM;
+  constexpr int VW = 16 / (int)sizeof(T);   // rows per 16-byte read
+  typedef T vT __attribute__((ext_vector_type(VW)));
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileGeom& tg = g.tg;
   SlabRow* ptab = (SlabRow*)smem_raw;
   SlabRow* qtab = ptab + tg.Pp;
   T* Us = (T*)(qtab + tg.Qp);
   T* Vs = Us + tg.u_len;
-  T* Ms = Vs + tg.v_len;                      // [tcolp][ldm]
+  const int mso = ((int)((unsigned char*)(Vs + tg.v_len) - smem_raw) + 15) & ~15;
+  T* Ms = (T*)(smem_raw + mso);               // [tcolp][ldm], rows of M contiguous
   T* As = Ms + (int64_t)tg.tcolp * g.ldm;     // [ip][lda] when staged
   const T* U = (const T*)mg.U;
   const T* V = (const T*)mg.V;
@@ -694,34 +697,49 @@ __global__ void __launch_bounds__(kRecThreads) reconstruct_k(MGen mg, const T* _
       const int ik_a = ib * 16 + lc;
       const bool oka = ik_a < g.Ik;
       const int ika = oka ? ik_a : 0;
-      const T* m0 = Ms + (cb0 * 16 + lc) * g.ldm;
+      // lane group kr takes rows k0 + VW kr .. + VW - 1 of its column in one
+      // 16-byte read and feeds VW MFMAs (the same row order for A and M)
+      const int kof = kr * VW;
+      const T* m0 = Ms + (cb0 * 16 + lc) * g.ldm + kof;
       const T* m1 = m0 + 16 * g.ldm;
-      if (two) {
-#pragma unroll 4
-        for (int k0 = 0; k0 < g.sp; k0 += MM::kStep) {
-          const int row = k0 + kr;
-          T a;
-          if (g.lda > 0) {
-            a = As[ik_a * g.lda + row];
-          } else {
+      const T* ar = g.lda > 0 ? As + ik_a * g.lda + kof : nullptr;
+      const T* ag = Au + (int64_t)ika * g.s + kof;
+      const bool avec = (g.s % VW) == 0;
+      auto load_a = [&](int k0) {
+        if (g.lda > 0) return *(const vT*)(ar + k0);
+        vT a;
+        if (avec) {
+          // rows are whole VW-groups here, so row < s covers all VW of them
+          a = (oka && k0 + kof < g.s) ? *(const vT*)(ag + k0) : vT{};
+        } else {
+#pragma unroll
+          for (int m = 0; m < VW; ++m) {
+            const int row = k0 + kof + m;
             const T av = Au[(int64_t)ika * g.s + min(row, g.s - 1)];
-            a = (oka && row < g.s) ? av : T(0);
+            a[m] = (oka && row < g.s) ? av : T(0);
           }
-          acc0 = MM::mma(a, m0[row], acc0);
-          acc1 = MM::mma(a, m1[row], acc1);
+        }
+        return a;
+      };
+      if (two) {
+#pragma unroll 2
+        for (int k0 = 0; k0 < g.sp; k0 += 4 * VW) {
+          const vT a = load_a(k0);
+          const vT b0 = *(const vT*)(m0 + k0);
+          const vT b1 = *(const vT*)(m1 + k0);
+#pragma unroll
+          for (int m = 0; m < VW; ++m) {
+            acc0 = MM::mma(a[m], b0[m], acc0);
+            acc1 = MM::mma(a[m], b1[m], acc1);
+          }
         }
       } else {
-#pragma unroll 4
-        for (int k0 = 0; k0 < g.sp; k0 += MM::kStep) {
-          const int row = k0 + kr;
-          T a;
-          if (g.lda > 0) {
-            a = As[ik_a * g.lda + row];
-          } else {
-            const T av = Au[(int64_t)ika * g.s + min(row, g.s - 1)];
-            a = (oka && row < g.s) ? av : T(0);
-          }
-          acc0 = MM::mma(a, m0[row], acc0);
+#pragma unroll 2
+        for (int k0 = 0; k0 < g.sp; k0 += 4 * VW) {
+          const vT a = load_a(k0);
+          const vT b0 = *(const vT*)(m0 + k0);
+#pragma unroll
+          for (int m = 0; m < VW; ++m) acc0 = MM::mma(a[m], b0[m], acc0);
         }
       }
 #pragma unroll
