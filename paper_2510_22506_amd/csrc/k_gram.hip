@@ -328,11 +328,20 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
             Xs[r * ldx + c] = (okc && r < xlim) ? xb[cr.off + (int64_t)r * xv.x_ik] : T(0);
         }
       } else {
-        for (int e = tid; e < tg.tcol * xrows; e += kGramThreads) {
-          const int r = e / tg.tcol, c = e - r * tg.tcol;
+        // element e = tid + i * kGramThreads of the row-major (r, c) walk,
+        // advanced without a division per element
+        const int dr = kGramThreads / tg.tcol, dc = kGramThreads - dr * tg.tcol;
+        int r = tid / tg.tcol, c = tid - r * tg.tcol;
+        while (r < xrows) {
           const SlabRow cr = ctab[c];
           Xs[r * ldx + c] = (cr.cl < lim_u && cr.map < lim_v && r < xlim)
                                 ? xb[cr.off + (int64_t)r * xv.x_ik] : T(0);
+          c += dc;
+          r += dr;
+          if (c >= tg.tcol) {
+            c -= tg.tcol;
+            ++r;
+          }
         }
       }
     }
