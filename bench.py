@@ -21,7 +21,9 @@ workload through the continuous-batching server (completions/s, p50/p99
 latency, split bf16 against float32 at saturation).  `rank_schedule` runs
 the rank-increasing schedule on the same workload (rank ones up to its ranks)
 and times one growth.  `roofline_xpass_large` is the X/mask pass on a 1 GiB
-tensor (larger than the Infinity Cache).  `cpu_baseline` is the float64
+tensor (larger than the Infinity Cache).  `other_workloads` times other
+configurations the same way (by default the 256x256x3 image, which is
+launch-bound).  `cpu_baseline` is the float64
 oracle on the host cores over a bounded number of sweeps of the same
 workload.
 
@@ -263,6 +265,38 @@ def rank_schedule(prob, prec, ext, sweeps=20):
                           "from": list(below), "to": list(rmax)}}
 
 
+def other_workload(name, steps=40, warmup=3):
+    """Sweeps/s of another configuration (default precision, reuse on), timed
+    like the main one, with its dominant kernel's roofline from an
+    event-bracketed pass."""
+    import torch
+    from paper_2510_22506_amd import Plan
+    from workloads import make_problem
+    prec = DEFAULT_PREC[name]
+    prob = make_problem(name, seed=0, precision=("f64" if prec == "f64" else "f32"))
+    plan = Plan(prob.dims, prob.ranks, prob.lam, prob.delta, prob.rho, precision=prec,
+                device="cuda:0", extrapolation=DEFAULT_EXTRAP.get(name))
+    plan.set_factors(prob.A0)
+    plan.set_observed(torch.from_numpy(prob.Y), torch.from_numpy(prob.mask))
+    plan.sweep(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.sweep(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.profile_enable(True)
+    plan.profile_read(reset=True)
+    plan.sweep(steps)
+    torch.cuda.synchronize()
+    prof = plan.profile_read(reset=True)
+    plan.close()
+    roofs = {k: stage_roofline(k, v, prec) for k, v in prof.items() if v["launches"]}
+    dom = max(roofs, key=lambda k: prof[k]["ms"])
+    return {"workload": f"{name}: {WORKLOADS[name][2]}", "dtype": prec, "steps": steps,
+            "value": steps / dt, "unit": "sweeps/s", "ms_per_step": dt / steps * 1e3,
+            "roofline": roofs[dom]}
+
+
 def cpu_baseline(prob, sweeps, ext=None):
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -299,6 +333,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-rank-schedule", action="store_true",
                     help="skip the rank-increasing schedule measurement")
+    ap.add_argument("--also", default="c2",
+                    help="comma-separated other workloads reported under 'other_workloads' "
+                         "('' for none; default: the 256x256x3 image)")
     ap.add_argument("--no-xpass-large", action="store_true",
                     help="skip the X/mask pass on a 1 GiB tensor")
     ap.add_argument("--serve-n", type=int, default=256)
@@ -410,6 +447,14 @@ def main():
             line["roofline_xpass_large"] = xpass_large()
         except Exception as e:  # reported, never hides the sweep measurement
             line["roofline_xpass_large"] = {"error": f"{type(e).__name__}: {e}"}
+    others = [w for w in args.also.split(",") if w and w != name]
+    if others:
+        line["other_workloads"] = {}
+        for w in others:
+            try:
+                line["other_workloads"][w] = other_workload(w)
+            except Exception as e:  # reported, never hides the main measurement
+                line["other_workloads"][w] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_rank_schedule:
         try:
             line["rank_schedule"] = rank_schedule(prob, prec, ext)
