@@ -45,7 +45,9 @@ __device__ __forceinline__ void static_for(F&& f) {
 // each), the right-hand sides (2 x 32 SB), reciprocal pivots (32 SB), the
 // back-substitution partials (64), a wave-sum buffer (16) and the column
 // counter of the diagonal block (one word).
-static inline size_t solve_lds_doubles(int sb) { return (size_t)67 * 32 * sb + 81; }
+static inline size_t solve_lds_doubles(int sb) {
+  return (size_t)67 * 32 * sb + 82 + (size_t)32 * (sb - 1) * 33;
+}
 
 // Layout: thread (r, cc) = (tid % 32, tid / 32) holds H[r + 32a][cc + 32b]
 // for the lower blocks b <= a in registers (32x32 cyclic over 1024 threads).
@@ -78,6 +80,7 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
   double* const tpart = rdiag + LDP;
   double* const red = tpart + 64;
   int* const pub = (int*)(red + 16);
+  double* const stg = red + 17;     // [32 (SB - 1)][33]: trailing-update tiles
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = tid & 31, cc = tid >> 5;
@@ -232,20 +235,40 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
 #pragma unroll
     for (int a = p + 1; a < SB; ++a) H[a][p] = pan[cc * LDP + r + 32 * a];
     if (nbelow > 0) {
-#pragma unroll 2
-      for (int jj = 0; jj < 32; ++jj) {
-        double li[SB], lm[SB];
+      // rank-32 update of the trailing blocks on FP64 MFMA, one column block
+      // b at a time: the product (rows 32b ..) x (columns 32b .. 32b + 31) of
+      // the finished panel with itself is formed in 16 x 16 tiles, staged in
+      // LDS, and subtracted from the cyclic register blocks H[a][b], a >= b
+      static_for<SB>([&](auto bc) __attribute__((always_inline)) {
+        constexpr int b = decltype(bc)::value;
+        if constexpr (b > p) {
+          if (32 * b < s) {
+            typedef Mfma<double> MD;
+            const int kr = lane >> 4, lc = lane & 15;
+            const int nrt = 2 * (SB - b);
+            for (int t = wave; t < 2 * nrt; t += 16) {
+              const int rt = t >> 1, ct = t & 1;
+              const int row0 = 32 * b + 16 * rt, col0 = 32 * b + 16 * ct;
+              typename MD::acc_t acc = MD::zero();
+              if (row0 < s) {
 #pragma unroll
-        for (int a = p + 1; a < SB; ++a) {
-          li[a] = pan[jj * LDP + r + 32 * a];
-          lm[a] = pan[jj * LDP + cc + 32 * a];
+                for (int k0 = 0; k0 < 32; k0 += 4) {
+                  const double av = pan[(k0 + kr) * LDP + row0 + lc];
+                  const double bv = pan[(k0 + kr) * LDP + col0 + lc];
+                  acc = MD::mma(av, bv, acc);
+                }
+              }
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                stg[(16 * rt + MD::row(lane, i)) * 33 + 16 * ct + lc] = acc[i];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a = b; a < SB; ++a) H[a][b] -= stg[(r + 32 * (a - b)) * 33 + cc];
+            __syncthreads();
+          }
         }
-#pragma unroll
-        for (int a = p + 1; a < SB; ++a)
-#pragma unroll
-          for (int b = p + 1; b <= a; ++b) H[a][b] -= li[a] * lm[b];
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      });
       for (int t = tid; t < 2 * nbelow; t += 1024) {
         const int v = t >= nbelow ? 1 : 0;
         const int m = p0 + 32 + t - v * nbelow;
