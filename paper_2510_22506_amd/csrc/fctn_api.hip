@@ -26,8 +26,6 @@ constexpr int kTargetGramWGs = 512;
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 inline int pad16(int x) { return (x + 15) / 16 * 16; }
-// leading dimension with ld % 64 == 16: conflict-free 16-lane x 4-row LDS reads
-inline int ld_pad(int x) { return x + ((16 - x % 64) % 64 + 64) % 64; }
 
 struct Carver {
   char* base;
