@@ -1,7 +1,8 @@
 """Continuous-batching server (fctn_server_*): each result of a mixed batch
 equals the same request run alone on a plan, bit for bit (the plans share no
-state and every kernel is deterministic); a float64 request in the mix
-matches the oracle; a small arena still admits every request by footprint;
+state and every kernel is deterministic), for orders 3, 4 and 5, four
+precisions and the asymmetric extrapolation; the float64 requests in the mix
+match the oracle; a small arena still admits every request by footprint;
 a request larger than the arena is rejected; a non-finite observed value is
 reported on the completion."""
 
@@ -25,7 +26,11 @@ MIX = [
     ("c4", (16, 14, 7), (6, 4, 4), "bf16x3"),
     ("c2", (20, 20, 3), (6, 3, 3), "f32"),
     ("c1", (8, 7, 5), None, "f64"),
+    ("c7", (6, 5, 4, 3, 4), (2,) * 10, "f32"),                # order 5
+    ("c6", (18, 16, 4, 5), (4, 3, 3, 3, 3, 2), "f64"),       # with extrapolation
 ]
+# the paper runs its multi-temporal images with the asymmetric extrapolation
+EXTRAP = {"c6": (0.5, 0.5)}
 
 
 def _request(tag, name, dims, ranks, prec, sweeps=6):
@@ -36,12 +41,14 @@ def _request(tag, name, dims, ranks, prec, sweeps=6):
              Y=torch.from_numpy(np.ascontiguousarray(p.Y)).to("cuda", elem),
              mask=torch.from_numpy(np.ascontiguousarray(p.mask.astype(np.uint8))).cuda(),
              A0=torch.from_numpy(np.concatenate([a.ravel() for a in p.A0])).cuda(),
-             sweeps=sweeps, lam=p.lam, delta=p.delta, rho=p.rho, precision=prec)
+             sweeps=sweeps, lam=p.lam, delta=p.delta, rho=p.rho, precision=prec,
+             extrapolation=EXTRAP.get(name))
     return p, r
 
 
 def _alone(r):
-    pl = fctn.Plan(r["dims"], r["ranks"], r["lam"], r["delta"], r["rho"], r["precision"])
+    pl = fctn.Plan(r["dims"], r["ranks"], r["lam"], r["delta"], r["rho"], r["precision"],
+                   extrapolation=r["extrapolation"])
     pl.set_factors_dev(r["A0"])
     pl.set_observed(r["Y"], r["mask"])
     pl.sweep(r["sweeps"])
@@ -51,7 +58,8 @@ def _alone(r):
 
 
 def _footprint(r):
-    d = fctn.make_desc(r["dims"], r["ranks"], r["lam"], r["delta"], r["rho"], r["precision"])
+    d = fctn.make_desc(r["dims"], r["ranks"], r["lam"], r["delta"], r["rho"], r["precision"],
+                       extrapolation=r["extrapolation"])
     return (fctn.fctn_workspace_bytes(d) + 255) // 256 * 256
 
 
@@ -68,7 +76,8 @@ def test_mix_equals_alone_bitwise_and_f64_matches_oracle():
         assert torch.equal(X, _alone(r)), r["tag"]
         if r["precision"] == "f64":
             Xo, _, _ = pam.complete(p.Y, p.mask != 0, p.ranks, p.lam, p.delta, p.rho,
-                                    r["sweeps"], p.A0, reuse=True, order_policy=1)
+                                    r["sweeps"], p.A0, reuse=True, order_policy=1,
+                                    extrapolation=r["extrapolation"])
             Xg = X.cpu().numpy()
             assert np.linalg.norm(Xg - Xo) <= 1e-9 * np.linalg.norm(Xo)
             np.testing.assert_array_equal(Xg[p.mask != 0], p.Y[p.mask != 0])
