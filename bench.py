@@ -352,8 +352,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU; multi-GPU sharding is design-only "
-              "(see the sharding section of the design notes). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU (the library has no multi-GPU path); "
+              "use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -51,7 +51,7 @@ typedef enum {
   FCTN_E_NOMEM = 2,        /* workspace smaller than fctn_workspace_bytes */
   FCTN_E_DEVICE = 3,       /* a HIP runtime call failed                   */
   FCTN_E_NUMERIC = 4,      /* non-finite observed value on Omega          */
-  FCTN_E_UNSUPPORTED = 5   /* valid for the method, not for this build    */
+  FCTN_E_UNSUPPORTED = 5   /* valid for the method, not supported here    */
 } fctn_status;
 
 typedef enum {
@@ -65,7 +65,7 @@ typedef struct fctn_plan_s* fctn_plan_t;
 
 /* Problem descriptor: the inputs of Algorithms 1-2 apart from Y and Omega. */
 typedef struct {
-  int32_t order;                    /* N; this build runs N = 3 .. 6         */
+  int32_t order;                    /* N; supported: N = 3 .. 6              */
   int64_t dims[FCTN_MAX_ORDER];     /* I_1 .. I_N, each >= 1                 */
   int32_t ranks[FCTN_MAX_BONDS];    /* r_FCTN in the order above, each >= 1  */
   double lambda[FCTN_MAX_ORDER];    /* lambda_k >= 0 (eq. model_1)           */

@@ -40,7 +40,7 @@ monotone.
 
 Rank-increasing schedule (Algorithms 1-2 take a maximal FCTN-rank and start
 from rank ones; the growth rule itself is deferred to the paper's reference
-[Zheng2022], so the rule here is this build's reading): after a sweep whose
+[Zheng2022], so the rule here is a reading of ours): after a sweep whose
 relative change is below tau, every bond rank below its maximum grows by one.
 Each grown bond (i, j), i < j, gets a new slice in both factors: factor i's new
 entries are fresh draws (standard normal, like the initial factors), factor

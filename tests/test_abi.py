@@ -53,7 +53,8 @@ def test_workspace_bytes_and_validation(F):
         assert F.fctn_workspace_bytes(b) == 0
     assert F.fctn_workspace_bytes(F.make_desc((32, 32, 8), (3, 3, 3), precision="f64",
                                               extrapolation=(0.5, 0.5))) == n
-    # valid for the method, outside this build: N = 7, N = 2, rank products above 192
+    # valid for the method, outside the library's support: N = 7, N = 2, rank
+    # products above 192
     assert F.fctn_workspace_bytes(F.make_desc((3,) * 7, (2,) * 21)) == 0
     assert F.fctn_workspace_bytes(F.make_desc((5, 4), (2,))) == 0
     assert F.fctn_workspace_bytes(F.make_desc((8, 8, 8), (16, 16, 2))) == 0
