@@ -327,7 +327,7 @@ def main():
                     help="alpha,beta of the asymmetric extrapolation, or 'off' "
                          "(default: on at 0.5,0.5 for c6, off otherwise)")
     ap.add_argument("--order-policy", type=int, default=1)
-    ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--cpu-sweeps", type=int, default=14)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="add the per-stage breakdown")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
