@@ -104,6 +104,14 @@ __device__ inline double rsqrt_f64(double d) {
   return y;
 }
 
+// 1/d for d > 0: hardware estimate refined by two Newton steps.
+__device__ inline double rcp_f64(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  y = fma(y, fma(-d, y, 1.0), y);
+  y = fma(y, fma(-d, y, 1.0), y);
+  return y;
+}
+
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace fctn

@@ -150,28 +150,91 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
     // (acquire) for column j.
     const int nbelow = max(s - p0 - 32, 0);
     if (wave == 0) {
+      // wave 0 parks its register blocks of H in the (idle) staging area for
+      // the duration of the column loop, which needs the registers
+      if constexpr (SB >= 3) {
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < SB; ++a)
+#pragma unroll
+          for (int b = 0; b <= a; ++b) stg[64 * t++ + lane] = H[a][b];
+      }
       const int i = lane & 31, h = lane >> 5;
       double d[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) d[q] = pan[(16 * h + q) * LDP + p0 + i];
+      // Column j in three parts, software-pipelined so that the LDS round
+      // trip of one column overlaps the pivot chain of the next:
+      //   pivot: readlane of the diagonal entry, L[i][j] = d * rsqrt(pivot),
+      //          stored to the panel;
+      //   fast path: column j + 1 (the next pivot's column) updated from
+      //          registers in unscaled form, d[i][j+1] -= d[i][j] d[j+1][j] /
+      //          pivot, so that the serial chain from one pivot to the next
+      //          holds a readlane, a reciprocal and one multiply-add;
+      //   rest: the other columns' multipliers L[16h + q][j] read back from
+      //          the panel (one address per half: broadcast reads) and
+      //          applied at the start of step j + 1.
+      // No branch inside the loop: rows and columns past np (last panel) are
+      // zero padding with a unit diagonal, so all they produce is zero.
 #pragma unroll
-      for (int j = 0; j < 32; ++j) {
-        if (j < np) {
-          const int hj = j >> 4, cj = j & 15;
-          const double piv = bcast_lane(d[cj], j + 32 * hj);
-          const double rs = rsqrt_f64(piv);
-          const double lv = i > j ? d[cj] * rs : 0.0;
-          if (h == hj) pan[j * LDP + p0 + i] = lv;
-          if (lane == 0) {
-            rdiag[p0 + j] = rs;
-            __hip_atomic_store(pub, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          const double lij = pan[j * LDP + p0 + i];
+      for (int q = 0; q < 16; ++q) d[q] = (i >= np && 16 * h + q == i) ? 1.0 : d[q];
+      double dn = d[0];     // column j of this lane's row, all updates applied
+      double pl[16], pli = 0.0;
+      double rsl = 0.0;
 #pragma unroll
-          for (int q = 0; q < 16; ++q) d[q] -= lij * pan[j * LDP + p0 + 16 * h + q];
+      for (int q = 0; q < 16; ++q) pl[q] = 0.0;
+      static_for<32>([&](auto jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int hj = j >> 4, jn = j + 1, hn = jn >> 4, cn = jn & 15;
+        // columns still open after column j - 1 (for j > 16 only those of
+        // the upper half above j - 1)
+        if constexpr (j > 0) {
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            if (j <= 16 || q >= j - 16) d[q] -= pli * pl[q];
         }
+        if constexpr (j == 16) dn = d[0];   // first column of the upper half
+        const double piv = bcast_lane(dn, j + 32 * hj);
+        const double rs = rsqrt_f64(piv);
+        rsl = i == j ? rs : rsl;
+        // L[i][j], valid in the half that holds column j (h == hj)
+        const double own = i > j ? dn * rs : 0.0;
+        *(h == hj ? pan + j * LDP + p0 + i : tpart + i) = own;
+        if constexpr (jn < 32 && hn == hj) {
+          const double lq = bcast_lane(own, jn + 32 * hj);
+          dn = d[cn] - (h == hn ? own : 0.0) * lq;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        pli = pan[j * LDP + p0 + i];
+        const double2* colj = (const double2*)(pan + j * LDP + p0 + 16 * h);
+#pragma unroll
+        for (int q2 = 0; q2 < 8; ++q2) {
+          if (j < 16 || 2 * q2 + 1 >= j - 15) {
+            const double2 v = colj[q2];
+            pl[2 * q2] = v.x;
+            pl[2 * q2 + 1] = v.y;
+          }
+        }
+        // the fast-path column is already done in its half
+        if constexpr (jn < 32 && hn == hj) pl[cn] = h == hn ? 0.0 : pl[cn];
+        // publish every fourth column: reciprocal pivots, then the counter
+        // (release: the columns and pivots are visible before it)
+        if constexpr ((j & 3) == 3) {
+          rdiag[p0 + i] = rsl;
+          __hip_atomic_store(pub, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        // the previous column's update is complete here (bounds the loads'
+        // live range)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) asm volatile("" ::"v"(d[q]));
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      if constexpr (SB >= 3) {
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < SB; ++a)
+#pragma unroll
+          for (int b = 0; b <= a; ++b) H[a][b] = stg[64 * t++ + lane];
       }
     } else if (wave != 4 && (wave - 1 - (wave > 4)) * 32 < nbelow + 2) {
       // rows 2 rp and 2 rp + 1 of the row list (rows below, then the two
