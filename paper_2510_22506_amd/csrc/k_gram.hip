@@ -229,11 +229,15 @@ __device__ inline void stage_operands(const MGen& mg, const TileGeom& tg, const 
 }
 
 // float32: at most 128 VGPRs, so that two workgroups share a CU and one
-// stages its next tile while the other runs MFMA (float64 keeps one per CU)
-template <typename T>
+// stages its next tile while the other runs MFMA (float64 keeps one per CU).
+// TPW output tiles per wave: 16 in general; 2 for the modes with at most 16
+// output tiles (small s_k), whose freed accumulator registers let the operand
+// and X staging keep kGatherBatch loads in flight per thread.
+template <typename T, int TPW>
 __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MGen mg, const T* __restrict__ X,
                                                            XView xv, GramGeom g,
                                                            T* __restrict__ part) {
+  constexpr bool kBatch = TPW <= 4;
   typedef Mfma<T> MM;
   constexpr int VW = 16 / (int)sizeof(T);   // columns per 16-byte LDS read
   typedef T vT __attribute__((ext_vector_type(VW)));
@@ -270,11 +274,11 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
 
   // this wave's output tiles (wave-uniform): bit 0 = A operand from X_(k),
   // bits 1-10 = row block bi, bits 11-20 = column block bj
-  int tdesc[kTPW];
-  bool valid[kTPW];
-  typename MM::acc_t acc[kTPW];
+  int tdesc[TPW];
+  bool valid[TPW];
+  typename MM::acc_t acc[TPW];
 #pragma unroll
-  for (int j = 0; j < kTPW; ++j) {
+  for (int j = 0; j < TPW; ++j) {
     const int t = t0 + wave + kGramWaves * j;
     valid[j] = t < t1;
     acc[j] = MM::zero();
@@ -311,15 +315,30 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
   FCTN_GRAM_MARK_INIT
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
-    stage_operands<T, false>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
-                             kGramThreads);
+    stage_operands<T, kBatch>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
+                              kGramThreads);
     FCTN_GRAM_MARK(0);
     if (xrows > 0) {
       const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
       const int64_t lim_u = mg.Cu - cu0, lim_v = mg.Cv - cv0;
       const T* xb = X + cu0 * xv.x_cu + cv0 * xv.x_cv + (int64_t)(ba_lo * 16) * xv.x_ik;
       const int xlim = xv.Ik - ba_lo * 16;
-      if (x_rfast) {
+      if constexpr (kBatch) {
+        // thread (c, r0): column c, rows r0, r0 + ngrp, ...
+        const int ngrp = kGramThreads / tg.tcol;
+        if (tid < ngrp * tg.tcol) {
+          gather2d<T>(
+              tid % tg.tcol, tg.tcol, tg.tcol, tid / tg.tcol, ngrp, xrows,
+              [&](int c, int r) {
+                const SlabRow cr = ctab[c];
+                T v = T(0);
+                if (cr.cl < lim_u && cr.map < lim_v && r < xlim)
+                  v = xb[cr.off + (int64_t)r * xv.x_ik];
+                return v;
+              },
+              [&](int c, int r, T v) { Xs[r * ldx + c] = v; });
+        }
+      } else if (x_rfast) {
         const int l = tid % xl, grp = tid / xl, ngrp = kGramThreads / xl;
         for (int c = grp; c < tg.tcol; c += ngrp) {
           const SlabRow cr = ctab[c];
@@ -358,7 +377,7 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
     // once, in the same order for both operands
     const int kof = (lane >> 4) * VW;
 #pragma unroll
-    for (int j = 0; j < kTPW; ++j) {
+    for (int j = 0; j < TPW; ++j) {
       if (valid[j]) {
         const int d = tdesc[j];
         const T* Ab = ((d & 1) ? Xs + (((d >> 1) & 1023) * 16 + (lane & 15)) * ldx
@@ -380,7 +399,7 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
   FCTN_GRAM_MARK_FLUSH
 
 #pragma unroll
-  for (int j = 0; j < kTPW; ++j) {
+  for (int j = 0; j < TPW; ++j) {
     if (valid[j]) {
       const int t = t0 + wave + kGramWaves * j;
       T* base = part + ((int64_t)split * g.nTiles + t) * 256;
@@ -560,11 +579,13 @@ int gram_max_lds_bytes() { return 160 * 1024; }
 hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView& xv,
                            const GramGeom& g, void* part, hipStream_t st) {
   dim3 grid(g.nSplit, g.nGroups);
+  // the small-tile variant covers a group's tiles only when all of them fit
+  const bool small = g.nGroups == 1 && g.nTiles <= kGramWaves * 2;
   if (prec == P_F64) {
-    hipFuncSetAttribute((const void*)gram_rhs_k<double>,
+    hipFuncSetAttribute((const void*)gram_rhs_k<double, kTPW>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    gram_rhs_k<double><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const double*)X, xv, g,
-                                                                (double*)part);
+    gram_rhs_k<double, kTPW><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const double*)X, xv,
+                                                                      g, (double*)part);
   } else if (prec == P_BF16) {
     hipFuncSetAttribute((const void*)gram_rhs_bf16_k<0>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
@@ -575,11 +596,16 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
     gram_rhs_bf16_k<1><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
                                                                 (float*)part);
-  } else {
-    hipFuncSetAttribute((const void*)gram_rhs_k<float>,
+  } else if (small) {
+    hipFuncSetAttribute((const void*)gram_rhs_k<float, 2>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    gram_rhs_k<float><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
-                                                               (float*)part);
+    gram_rhs_k<float, 2><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
+                                                                  (float*)part);
+  } else {
+    hipFuncSetAttribute((const void*)gram_rhs_k<float, kTPW>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
+    gram_rhs_k<float, kTPW><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
+                                                                     (float*)part);
   }
   return hipGetLastError();
 }
