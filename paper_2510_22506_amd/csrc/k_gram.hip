@@ -424,7 +424,7 @@ int gram_tiles_per_group() { return kGramWaves * kTPW; }
 // bf16: at most 128 VGPRs (two workgroups per CU, as for float32); the split
 // form keeps the default budget (its tiles need more than half a CU's LDS,
 // so it runs one workgroup per CU anyway)
-template <int X3>
+template <int X3, int TPW>
 __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen mg, const float* __restrict__ X,
                                                                 XView xv, GramGeom g,
                                                                 float* __restrict__ part) {
@@ -461,11 +461,11 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
   // this wave's output tiles (wave-uniform): bit 0 = A operand from X_(k),
   // bits 1-10 = row block bi, bits 11-20 = column block bj; the lane's own
   // offset inside a 16-row block is loff
-  int tdesc[kTPW];
-  bool valid[kTPW];
-  MF::acc_t acc[kTPW];
+  int tdesc[TPW];
+  bool valid[TPW];
+  MF::acc_t acc[TPW];
 #pragma unroll
-  for (int j = 0; j < kTPW; ++j) {
+  for (int j = 0; j < TPW; ++j) {
     const int t = t0 + wave + kGramWaves * j;
     valid[j] = t < t1;
     acc[j] = MF::zero();
@@ -539,7 +539,7 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
     __syncthreads();
     for (int kk = 0; kk < tg.tcolp; kk += 32) {
 #pragma unroll
-      for (int j = 0; j < kTPW; ++j) {
+      for (int j = 0; j < TPW; ++j) {
         if (valid[j]) {
           const int d = tdesc[j];
           const int ao = ((d >> 1) & 1023) * 16 * ldb + loff + kk;
@@ -564,7 +564,7 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
   }
 
 #pragma unroll
-  for (int j = 0; j < kTPW; ++j) {
+  for (int j = 0; j < TPW; ++j) {
     if (valid[j]) {
       const int t = t0 + wave + kGramWaves * j;
       float* base = part + ((int64_t)split * g.nTiles + t) * 256;
@@ -586,16 +586,23 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
     gram_rhs_k<double, kTPW><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const double*)X, xv,
                                                                       g, (double*)part);
-  } else if (prec == P_BF16) {
-    hipFuncSetAttribute((const void*)gram_rhs_bf16_k<0>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    gram_rhs_bf16_k<0><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
-                                                                (float*)part);
-  } else if (prec == P_BF16X3) {
-    hipFuncSetAttribute((const void*)gram_rhs_bf16_k<1>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    gram_rhs_bf16_k<1><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
-                                                                (float*)part);
+  } else if (prec == P_BF16 || prec == P_BF16X3) {
+    const void* kf = prec == P_BF16
+                         ? (small ? (const void*)gram_rhs_bf16_k<0, 2> : (const void*)gram_rhs_bf16_k<0, kTPW>)
+                         : (small ? (const void*)gram_rhs_bf16_k<1, 2> : (const void*)gram_rhs_bf16_k<1, kTPW>);
+    hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
+    if (prec == P_BF16 && small)
+      gram_rhs_bf16_k<0, 2><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
+                                                                     (float*)part);
+    else if (prec == P_BF16)
+      gram_rhs_bf16_k<0, kTPW><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv,
+                                                                        g, (float*)part);
+    else if (small)
+      gram_rhs_bf16_k<1, 2><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
+                                                                     (float*)part);
+    else
+      gram_rhs_bf16_k<1, kTPW><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv,
+                                                                        g, (float*)part);
   } else if (small) {
     hipFuncSetAttribute((const void*)gram_rhs_k<float, 2>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
