@@ -404,6 +404,14 @@ void fill_tile(const MGen& mg, int TCu, int TCv, int kalign, TileGeom* tg) {
   // staging lanes along the slab's contiguous index (at most 64)
   tg->u_lw = floor_log2(std::min(tg->us_k == 1 ? tg->Kp : tg->Pp, 64));
   tg->v_lw = floor_log2(std::min(tg->vs_k == 1 ? tg->Kp : tg->Qp, 64));
+  // 16-byte staging of [kap][p] slabs: ru contiguous and R a multiple of 4,
+  // every other stride a multiple of 4 elements, so that each run of four
+  // rows is 16-byte aligned (the operand base pointers are checked at launch)
+  auto vec_ok = [&](int64_t f_r, int64_t f_c, int64_t f_k, int R, bool k_fast) {
+    return !k_fast && f_r == 1 && R % 4 == 0 && f_c % 4 == 0 && f_k % 4 == 0;
+  };
+  tg->u_vec = vec_ok(mg.u_ru, mg.u_cu, mg.u_k, mg.Ru, tg->us_k == 1) ? 1 : 0;
+  tg->v_vec = vec_ok(mg.v_rv, mg.v_cv, mg.v_k, mg.Rv, tg->vs_k == 1) ? 1 : 0;
   tg->nTileU = (mg.Cu + TCu - 1) / TCu;
   tg->nTileV = (mg.Cv + TCv - 1) / TCv;
   tg->nColTiles = tg->nTileU * tg->nTileV;

@@ -121,13 +121,33 @@ __device__ inline void gather2d(int x0, int sx, int nx, int y0, int sy, int ny, 
 // along the slab's contiguous index (2^lw of them).  kBatched: loads issued in
 // batches (gather2d); the float32 Gram kernel, which has no registers to
 // spare at two workgroups per CU, stages one element per thread at a time.
-template <typename T, bool kBatched>
+template <typename T, bool kBatched, bool kVec = false>
 __device__ inline void stage_slab(const T* __restrict__ F, int64_t base, int64_t f_k, int K,
-                                  int Kp, int Pp, int s_k, int s_p, int lw,
+                                  int Kp, int Pp, int s_k, int s_p, int lw, bool vec,
                                   const SlabRow* __restrict__ tab, int64_t lim,
                                   T* __restrict__ S, int tid, int nth) {
   const int lanes = 1 << lw, lane = tid & (lanes - 1), grp = tid >> lw, ngrp = nth >> lw;
   const T* Fb = F + base;
+  if constexpr (kVec && !kBatched && sizeof(T) == 4) {
+    if (vec) {
+      // [kap][p] slab in runs of four rows p: one 16-byte load and store
+      // each (run structure and alignment checked on the host)
+      typedef T v4 __attribute__((ext_vector_type(4)));
+      const int n4 = Pp >> 2;
+      const int lw4 = 31 - __builtin_clz(n4 < 64 ? n4 : 64);
+      const int l4 = tid & ((1 << lw4) - 1), g4 = tid >> lw4, ng4 = nth >> lw4;
+      for (int k = g4; k < Kp; k += ng4) {
+        const bool okk = k < K;
+        for (int p = 4 * l4; p < Pp; p += 4 << lw4) {
+          const SlabRow r = tab[p];
+          v4 v = {T(0), T(0), T(0), T(0)};
+          if (okk && r.cl < lim) v = *(const v4*)(Fb + r.off + (int64_t)k * f_k);
+          *(v4*)(S + k * s_k + p) = v;
+        }
+      }
+      return;
+    }
+  }
   if constexpr (!kBatched) {
     if (s_k == 1) {                     // [p][kap]: lanes along kap
       for (int p = grp; p < Pp; p += ngrp) {
@@ -209,21 +229,21 @@ __device__ inline void mgen_mfma(const TileGeom& tg, const T* __restrict__ Us,
                      nwaves);
 }
 
-template <typename T, bool kBatched>
+template <typename T, bool kBatched, bool kVec = false>
 __device__ inline void stage_operands(const MGen& mg, const TileGeom& tg, const T* U, const T* V,
                                       int64_t tu, int64_t tv, int64_t& cur_tu, int64_t& cur_tv,
                                       T* Us, T* Vs, const SlabRow* ptab, const SlabRow* qtab,
                                       int tid, int nth) {
   if (tu != cur_tu) {
     const int64_t cu0 = tu * tg.TCu;
-    stage_slab<T, kBatched>(U, cu0 * mg.u_cu, mg.u_k, mg.K, tg.Kp, tg.Pp, tg.us_k, tg.us_p, tg.u_lw, ptab,
-                  mg.Cu - cu0, Us, tid, nth);
+    stage_slab<T, kBatched, kVec>(U, cu0 * mg.u_cu, mg.u_k, mg.K, tg.Kp, tg.Pp, tg.us_k, tg.us_p, tg.u_lw,
+                            tg.u_vec != 0, ptab, mg.Cu - cu0, Us, tid, nth);
     cur_tu = tu;
   }
   if (tv != cur_tv) {
     const int64_t cv0 = tv * tg.TCv;
-    stage_slab<T, kBatched>(V, cv0 * mg.v_cv, mg.v_k, mg.K, tg.Kp, tg.Qp, tg.vs_k, tg.vs_q, tg.v_lw, qtab,
-                  mg.Cv - cv0, Vs, tid, nth);
+    stage_slab<T, kBatched, kVec>(V, cv0 * mg.v_cv, mg.v_k, mg.K, tg.Kp, tg.Qp, tg.vs_k, tg.vs_q, tg.v_lw,
+                            tg.v_vec != 0, qtab, mg.Cv - cv0, Vs, tid, nth);
     cur_tv = tv;
   }
 }
@@ -233,7 +253,7 @@ __device__ inline void stage_operands(const MGen& mg, const TileGeom& tg, const 
 // TPW output tiles per wave: 16 in general; 2 for the modes with at most 16
 // output tiles (small s_k), whose freed accumulator registers let the operand
 // and X staging keep kGatherBatch loads in flight per thread.
-template <typename T, int TPW>
+template <typename T, int TPW, bool VEC = false>
 __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MGen mg, const T* __restrict__ X,
                                                            XView xv, GramGeom g,
                                                            T* __restrict__ part) {
@@ -315,7 +335,7 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
   FCTN_GRAM_MARK_INIT
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
-    stage_operands<T, kBatch>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
+    stage_operands<T, kBatch, VEC>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
                               kGramThreads);
     FCTN_GRAM_MARK(0);
     if (xrows > 0) {
@@ -577,7 +597,10 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
 int gram_max_lds_bytes() { return 160 * 1024; }
 
 hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView& xv,
-                           const GramGeom& g, void* part, hipStream_t st) {
+                           const GramGeom& g_in, void* part, hipStream_t st) {
+  GramGeom g = g_in;
+  if ((uintptr_t)mg.U % 16 != 0) g.tg.u_vec = 0;
+  if ((uintptr_t)mg.V % 16 != 0) g.tg.v_vec = 0;
   dim3 grid(g.nSplit, g.nGroups);
   // the small-tile variant covers a group's tiles only when all of them fit
   const bool small = g.nGroups == 1 && g.nTiles <= kGramWaves * 2;
@@ -608,6 +631,13 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
     gram_rhs_k<float, 2><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
                                                                   (float*)part);
+  } else if (g.tg.u_vec || g.tg.v_vec) {
+    // a separate instance, so that the 16-byte staging code does not cost
+    // the other modes' kernel registers
+    hipFuncSetAttribute((const void*)gram_rhs_k<float, kTPW, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
+    gram_rhs_k<float, kTPW, true><<<grid, kGramThreads, g.lds_bytes, st>>>(
+        mg, (const float*)X, xv, g, (float*)part);
   } else {
     hipFuncSetAttribute((const void*)gram_rhs_k<float, kTPW>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);

@@ -37,6 +37,8 @@ struct TileGeom {
   int32_t u_len, v_len;           // slab sizes (elements)
   int32_t u_lw, v_lw;             // log2 of the lanes that run along a slab's
                                   // contiguous index when staging it
+  int32_t u_vec, v_vec;           // float32 [kap][p] slab stageable with
+                                  // 16-byte loads (rows in aligned runs of 4)
   int64_t nTileU, nTileV, nColTiles;
 };
 
