@@ -25,6 +25,7 @@ SHAPES = [
     ((40, 24, 5), (12, 12, 4)),               # s_1 = 144: two output groups
     ((13, 11, 3, 7), (4, 2, 3, 2, 3, 2)),     # order 4, small ranks
     ((24, 28, 3, 6), (8, 3, 8, 3, 8, 3)),     # order 4 with the C3 ranks (s = 192)
+    ((31, 29, 3, 20), (2, 2, 4, 2, 4, 4)),    # mode 4: 16-byte slab staging, ragged last tile
     ((9, 7, 3, 4, 5), (2, 3, 1, 2, 3, 1, 2, 2, 1, 3)),            # order 5
     ((4, 3, 5, 2, 3, 4), (2, 1, 2, 2, 1, 2, 1, 2, 3, 1, 2, 2, 2, 1, 2)),  # order 6
 ]
