@@ -119,8 +119,10 @@ __device__ inline void gather2d(int x0, int sx, int nx, int y0, int sy, int ny, 
 // Stage one operand slab S(kap, p) = F[tab[p].off + base + kap * f_k] (zero
 // in the padding and beyond the tensor edge: tab[p].cl >= lim).  Lanes run
 // along the slab's contiguous index (2^lw of them).  kBatched: loads issued in
-// batches (gather2d); the float32 Gram kernel, which has no registers to
-// spare at two workgroups per CU, stages one element per thread at a time.
+// batches (gather2d); the general float32 Gram kernel, which has no registers
+// to spare at two workgroups per CU, stages one element per thread at a time,
+// or, in its kVec instance and for a [kap][p] slab whose rows come in aligned
+// runs of four (vec), four at a time with 16-byte loads and stores.
 template <typename T, bool kBatched, bool kVec = false>
 __device__ inline void stage_slab(const T* __restrict__ F, int64_t base, int64_t f_k, int K,
                                   int Kp, int Pp, int s_k, int s_p, int lw, bool vec,
@@ -252,7 +254,9 @@ __device__ inline void stage_operands(const MGen& mg, const TileGeom& tg, const 
 // stages its next tile while the other runs MFMA (float64 keeps one per CU).
 // TPW output tiles per wave: 16 in general; 2 for the modes with at most 16
 // output tiles (small s_k), whose freed accumulator registers let the operand
-// and X staging keep kGatherBatch loads in flight per thread.
+// and X staging keep kGatherBatch loads in flight per thread.  VEC: the
+// instance with 16-byte staging of [kap][p] slabs, kept separate because its
+// extra code raises the kernel's register spills.
 template <typename T, int TPW, bool VEC = false>
 __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MGen mg, const T* __restrict__ X,
                                                            XView xv, GramGeom g,

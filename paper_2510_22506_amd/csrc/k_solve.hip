@@ -55,8 +55,9 @@ static inline size_t solve_lds_doubles(int sb) {
 // pan[jj][i] = H[i][32p + jj], so that a half-wave reads 32 consecutive rows.
 // Per panel, with a workgroup barrier after (a)+(b) and after (c):
 //   (a) wave 0 factors the 32x32 diagonal block column by column; lanes
-//       (i, h) hold row i, columns 16h .. 16h + 15; each finished column is
-//       broadcast through LDS within the wave (no workgroup barrier);
+//       (i, h) hold row i, columns 16h .. 16h + 15; the next pivot's column
+//       is updated from registers (readlane), the others from the finished
+//       column read back from LDS one step later (no workgroup barrier);
 //   (b) meanwhile other waves solve the rows below the block, and the two
 //       right-hand-side rows, against the block's factor (TRSM), following
 //       the published columns through an LDS counter;
