@@ -613,40 +613,26 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
     gram_rhs_k<double, kTPW><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const double*)X, xv,
                                                                       g, (double*)part);
-  } else if (prec == P_BF16 || prec == P_BF16X3) {
-    const void* kf = prec == P_BF16
-                         ? (small ? (const void*)gram_rhs_bf16_k<0, 2> : (const void*)gram_rhs_bf16_k<0, kTPW>)
-                         : (small ? (const void*)gram_rhs_bf16_k<1, 2> : (const void*)gram_rhs_bf16_k<1, kTPW>);
-    hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    if (prec == P_BF16 && small)
-      gram_rhs_bf16_k<0, 2><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
-                                                                     (float*)part);
-    else if (prec == P_BF16)
-      gram_rhs_bf16_k<0, kTPW><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv,
-                                                                        g, (float*)part);
-    else if (small)
-      gram_rhs_bf16_k<1, 2><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
-                                                                     (float*)part);
-    else
-      gram_rhs_bf16_k<1, kTPW><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv,
-                                                                        g, (float*)part);
-  } else if (small) {
-    hipFuncSetAttribute((const void*)gram_rhs_k<float, 2>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    gram_rhs_k<float, 2><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
-                                                                  (float*)part);
-  } else if (g.tg.u_vec || g.tg.v_vec) {
-    // a separate instance, so that the 16-byte staging code does not cost
-    // the other modes' kernel registers
-    hipFuncSetAttribute((const void*)gram_rhs_k<float, kTPW, true>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    gram_rhs_k<float, kTPW, true><<<grid, kGramThreads, g.lds_bytes, st>>>(
-        mg, (const float*)X, xv, g, (float*)part);
   } else {
-    hipFuncSetAttribute((const void*)gram_rhs_k<float, kTPW>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    gram_rhs_k<float, kTPW><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const float*)X, xv, g,
-                                                                     (float*)part);
+    // float32 data: one kernel instance per (precision form, tile variant)
+    auto run = [&](auto kern) {
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)g.lds_bytes);
+      hipLaunchKernelGGL(kern, grid, dim3(kGramThreads), g.lds_bytes, st, mg, (const float*)X,
+                         xv, g, (float*)part);
+    };
+    if (prec == P_BF16)
+      run(small ? gram_rhs_bf16_k<0, 2> : gram_rhs_bf16_k<0, kTPW>);
+    else if (prec == P_BF16X3)
+      run(small ? gram_rhs_bf16_k<1, 2> : gram_rhs_bf16_k<1, kTPW>);
+    else if (small)
+      run(gram_rhs_k<float, 2>);
+    else if (g.tg.u_vec || g.tg.v_vec)
+      // a separate instance, so that the 16-byte staging code does not cost
+      // the other modes' kernel registers
+      run(gram_rhs_k<float, kTPW, true>);
+    else
+      run(gram_rhs_k<float, kTPW>);
   }
   return hipGetLastError();
 }
