@@ -120,9 +120,10 @@ __device__ inline void gather2d(int x0, int sx, int nx, int y0, int sy, int ny, 
 // in the padding and beyond the tensor edge: tab[p].cl >= lim).  Lanes run
 // along the slab's contiguous index (2^lw of them).  kBatched: loads issued in
 // batches (gather2d); the general float32 Gram kernel, which has no registers
-// to spare at two workgroups per CU, stages one element per thread at a time,
-// or, in its kVec instance and for a [kap][p] slab whose rows come in aligned
-// runs of four (vec), four at a time with 16-byte loads and stores.
+// to spare at two workgroups per CU, stages one element per thread at a time.
+// kVec (that kernel's second instance, and the reconstruction): a [kap][p]
+// slab whose rows come in aligned runs of four (vec) is staged four at a time
+// with 16-byte loads and stores instead.
 template <typename T, bool kBatched, bool kVec = false>
 __device__ inline void stage_slab(const T* __restrict__ F, int64_t base, int64_t f_k, int K,
                                   int Kp, int Pp, int s_k, int s_p, int lw, bool vec,
@@ -130,7 +131,7 @@ __device__ inline void stage_slab(const T* __restrict__ F, int64_t base, int64_t
                                   T* __restrict__ S, int tid, int nth) {
   const int lanes = 1 << lw, lane = tid & (lanes - 1), grp = tid >> lw, ngrp = nth >> lw;
   const T* Fb = F + base;
-  if constexpr (kVec && !kBatched && sizeof(T) == 4) {
+  if constexpr (kVec && sizeof(T) == 4) {
     if (vec) {
       // [kap][p] slab in runs of four rows p: one 16-byte load and store
       // each (run structure and alignment checked on the host)
@@ -707,7 +708,7 @@ hipError_t launch_reduce_gb(int prec, const GramGeom& g, const void* part, const
 constexpr int kRecThreads = 512;
 constexpr int kRecWaves = kRecThreads / 64;
 
-template <typename T>
+template <typename T, bool VEC = false>
 __global__ void __launch_bounds__(kRecThreads) reconstruct_k(MGen mg, const T* __restrict__ Au,
                                                              T* __restrict__ Z, XView xv,
                                                              RecGeom g) {
@@ -747,7 +748,7 @@ __global__ void __launch_bounds__(kRecThreads) reconstruct_k(MGen mg, const T* _
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
     const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
-    stage_operands<T, true>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
+    stage_operands<T, true, VEC>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
                             kRecThreads);
     __syncthreads();
     mgen_mfma<T>(tg, Us, Vs, ptab, qtab, Ms, lane, wave, kRecWaves);
@@ -827,12 +828,22 @@ __global__ void __launch_bounds__(kRecThreads) reconstruct_k(MGen mg, const T* _
 }
 
 hipError_t launch_reconstruct(int prec, const MGen& mg, const void* Au, void* Z,
-                              const XView& xv, const RecGeom& g, hipStream_t st) {
+                              const XView& xv, const RecGeom& g_in, hipStream_t st) {
+  RecGeom g = g_in;
+  if ((uintptr_t)mg.U % 16 != 0) g.tg.u_vec = 0;
+  if ((uintptr_t)mg.V % 16 != 0) g.tg.v_vec = 0;
   if (prec == P_F64) {
     hipFuncSetAttribute((const void*)reconstruct_k<double>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
     reconstruct_k<double><<<g.nblk, kRecThreads, g.lds_bytes, st>>>(mg, (const double*)Au,
                                                                     (double*)Z, xv, g);
+  } else if (g.tg.u_vec || g.tg.v_vec) {
+    // a separate instance, as for the Gram: the 16-byte staging code costs
+    // registers that the other modes would pay for
+    hipFuncSetAttribute((const void*)reconstruct_k<float, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
+    reconstruct_k<float, true><<<g.nblk, kRecThreads, g.lds_bytes, st>>>(mg, (const float*)Au,
+                                                                         (float*)Z, xv, g);
   } else {
     hipFuncSetAttribute((const void*)reconstruct_k<float>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
