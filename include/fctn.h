@@ -29,7 +29,10 @@
  *   - Calls are asynchronous on the plan's HIP stream, except those that
  *     fill host-side results (stats, flags); those synchronize the stream.
  *   - Every call returns fctn_status; nothing throws across the boundary.
- *     After FCTN_E_DEVICE the plan is unusable (the error is sticky).
+ *     After FCTN_E_DEVICE the plan is unusable (the error is sticky).  Besides
+ *     failed HIP calls, FCTN_E_DEVICE reports a kernel whose bounded internal
+ *     wait gave up (its result is then invalid); that is detected at the
+ *     next call that synchronizes to return host-side results.
  *   - Calls on one plan are not thread-safe; distinct plans are independent.
  */
 #ifndef FCTN_H
@@ -72,9 +75,20 @@ typedef struct {
   double delta[FCTN_MAX_ORDER];     /* delta_k > 0 (L_k, Section 3.1)        */
   double rho;                       /* proximal weight rho > 0 (eq. 3)       */
   int32_t precision;                /* fctn_precision                        */
-  int32_t reuse;                    /* 0: Algorithm 1 (every sub-network and
-                                       FCTN(A) from scratch); 1: Algorithm 2
-                                       (cached pair tensors, X from M'_last) */
+  int32_t reuse;                    /* 1: Algorithm 2 (Section 3.3): for
+                                       N = 4 the pair tensors A1xA2 and A3xA4
+                                       are cached and rebuilt only when one of
+                                       their factors changed.  0: Algorithm 1's
+                                       work: every mode's sub-network and the
+                                       FCTN(A) of the X step are contracted
+                                       from the factors, rebuilding the pair
+                                       (N = 4) each time.  Both run the same
+                                       kernels on the same operands, so their
+                                       iterates are bitwise equal; only the
+                                       contraction work differs (Table 1).  For
+                                       N = 3 nothing is cached and the flag has
+                                       no effect; for N = 5, 6 the operand
+                                       groups are rebuilt every mode in both */
   int32_t order_policy;             /* 0: factor order 1..N every sweep;
                                        1: for N = 4 alternate (1,2,3,4) and
                                        (3,4,1,2) so a cached pair carries over
@@ -160,10 +174,16 @@ fctn_status fctn_sweep(fctn_plan_t plan, int32_t nsweeps,
  * on that plan alone, bit for bit. */
 fctn_status fctn_sweep_many(fctn_plan_t* plans, int32_t count, int32_t nsweeps);
 
-/* Run up to max_sweeps sweeps, stopping after the first sweep whose relative
- * change is <= tol (tol <= 0: exactly max_sweeps sweeps; the test runs every
- * `check_every` sweeps, >= 1).  Copies X to X_out_dev if not NULL.  Fills
- * stats_host if not NULL (synchronizes). */
+/* Algorithms 1-2 run to their stopping rule (Section 3.2: stop once
+ * ||X^{t+1} - X^t||_F / ||X^t||_F <= epsilon, or after the iteration limit).
+ * Runs up to max_sweeps sweeps, stopping after the first sweep whose relative
+ * change is <= tol (tol <= 0: exactly max_sweeps sweeps).  The test reads the
+ * relative change back to the host every `check_every` sweeps (>= 1), so with
+ * check_every > 1 the run stops at the first multiple of check_every whose
+ * sweep passes the test.  Copies X to X_out_dev if not NULL.  Fills
+ * stats_host if not NULL; then the call synchronizes the stream, X_out
+ * included.  Errors: FCTN_E_INVALID for a NULL plan, max_sweeps < 0 or
+ * check_every < 1; FCTN_E_DEVICE (sticky) if a HIP call fails. */
 fctn_status fctn_complete(fctn_plan_t plan, int32_t max_sweeps, double tol,
                           int32_t check_every, void* X_out_dev,
                           fctn_stats* stats_host);
@@ -245,8 +265,10 @@ typedef struct {
 
 typedef struct {
   uint64_t tag;
-  int32_t status;           /* FCTN_OK, or FCTN_E_NUMERIC: a non-finite
-                               observed value (the sweeps still ran)          */
+  int32_t status;           /* FCTN_OK; FCTN_E_NUMERIC: a non-finite
+                               observed value (the sweeps still ran);
+                               FCTN_E_DEVICE: a kernel's bounded wait gave
+                               up, the result is invalid                      */
   int32_t sweeps_done;
   double rel_change;        /* of the last sweep (eq. 10 stopping quantity)   */
   double objective;         /* f after the last sweep (Section 3.5)           */

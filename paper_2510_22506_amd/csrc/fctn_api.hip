@@ -80,6 +80,7 @@ struct fctn_plan_s {
   uint32_t* bits;
   int32_t* bad_part;
   int32_t* bad_flag;
+  int32_t* dev_err;  // set by a kernel whose bounded wait gave up
   int bad_nblk;
   double* A64[FCTN_MAX_ORDER];
   void* Aw[FCTN_MAX_ORDER];
@@ -568,6 +569,7 @@ size_t carve(fctn_plan_s* P, char* base) {
   P->bad_nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (P->numel + 255) / 256));
   P->bad_part = (int32_t*)c.take(P->bad_nblk * sizeof(int32_t));
   P->bad_flag = (int32_t*)c.take(sizeof(int32_t));
+  P->dev_err = (int32_t*)c.take(sizeof(int32_t));
   int64_t smax = 1, imax = 1;
   P->max_cls = 1;
   size_t part_bytes = 0;
@@ -776,7 +778,7 @@ fctn_status solve(fctn_plan_s* P, int k, const double* G, const double* B) {
              8.0 * (m.s * m.s + 2.0 * m.Ik * m.s),
              launch_solve_classes(G, (int32_t)m.Ik, (int32_t)m.s, P->d.lambda[k],
                                   P->d.delta[k], P->d.rho, P->At,
-                                  P->trace_part + (size_t)k * P->max_cls, P->st));
+                                  P->trace_part + (size_t)k * P->max_cls, P->dev_err, P->st));
   // with the asymmetric extrapolation the epilogue also reads the proximal
   // centre A_k^t (overwritten in place), and the trace term the solve wrote
   // for the un-extrapolated factor is recomputed for the new one
@@ -847,13 +849,27 @@ fctn_status one_sweep(fctn_plan_s* P) {
   return FCTN_OK;
 }
 
-fctn_status read_slot(fctn_plan_s* P, const double* slot, fctn_sweep_stats* out) {
-  double h[4];
-  if (hipMemcpyAsync(h, slot, sizeof(h), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
-      hipStreamSynchronize(P->st) != hipSuccess) {
+// Synchronizes the plan's stream and reports a kernel-side failure (the
+// device error word) as FCTN_E_DEVICE, sticky.
+fctn_status sync_checked(fctn_plan_s* P) {
+  int32_t err = 0;
+  if (hipMemcpyAsync(&err, P->dev_err, sizeof(err), hipMemcpyDeviceToHost, P->st) !=
+          hipSuccess ||
+      hipStreamSynchronize(P->st) != hipSuccess || err != 0) {
     P->sticky = FCTN_E_DEVICE;
     return FCTN_E_DEVICE;
   }
+  return FCTN_OK;
+}
+
+fctn_status read_slot(fctn_plan_s* P, const double* slot, fctn_sweep_stats* out) {
+  double h[4];
+  if (hipMemcpyAsync(h, slot, sizeof(h), hipMemcpyDeviceToHost, P->st) != hipSuccess) {
+    P->sticky = FCTN_E_DEVICE;
+    return FCTN_E_DEVICE;
+  }
+  fctn_status v = sync_checked(P);
+  if (v != FCTN_OK) return v;
   out->rel_change = h[0];
   out->f_data = h[1];
   out->f_trace = h[2];
@@ -1145,6 +1161,11 @@ fctn_status fctn_complete(fctn_plan_t P, int32_t max_sweeps, double tol, int32_t
     if (done > 0 && !have_last) {
       fctn_status s = read_slot(P, P->hist + ((P->sweeps_done - 1) % kHist) * 4, &last);
       if (s != FCTN_OK) return s;
+    } else if (X_out_dev) {
+      // the X_out copy was queued after the last stopping-rule read: a caller
+      // that asked for host stats gets a finished X_out as well
+      fctn_status s = sync_checked(P);
+      if (s != FCTN_OK) return s;
     }
     stats_host->rel_change = done > 0 ? last.rel_change : 0.0;
     stats_host->objective = done > 0 ? last.objective : 0.0;
@@ -1213,11 +1234,12 @@ fctn_status fctn_step_solve(fctn_plan_t P, int32_t k, const double* G_dev, const
     const int nc = P->mode[k].ncls;
     std::vector<double> tp(nc);
     if (hipMemcpyAsync(tp.data(), P->trace_part + (size_t)k * P->max_cls, nc * sizeof(double),
-                       hipMemcpyDeviceToHost, P->st) != hipSuccess ||
-        hipStreamSynchronize(P->st) != hipSuccess) {
+                       hipMemcpyDeviceToHost, P->st) != hipSuccess) {
       P->sticky = FCTN_E_DEVICE;
       return FCTN_E_DEVICE;
     }
+    fctn_status v = sync_checked(P);
+    if (v != FCTN_OK) return v;
     double t = 0.0;
     for (double v : tp) t += v;
     *trace_host = t;
@@ -1352,7 +1374,8 @@ struct fctn_server_s {
   std::vector<SrvSlot> slots;
   std::deque<SrvPending> queue;
   std::vector<hipEvent_t> pool;
-  int32_t* pin_flag = nullptr;  // pinned host memory, one flag per slot
+  int32_t* pin_flag = nullptr;  // pinned host memory, two flags per slot: the
+                                // non-finite flag of Y and the device error word
   double* pin_stats = nullptr;  // pinned host memory, four doubles per slot
   fctn_status sticky = FCTN_OK;
 };
@@ -1413,7 +1436,7 @@ fctn_status srv_admit(fctn_server_s* S, int slot, const SrvPending& h, size_t of
   if (v != FCTN_OK) return v;
   v = set_factors_dev(P, h.r.A0_dev);
   if (v == FCTN_OK) v = set_observed_async(P, h.r.Y_dev, h.r.mask_dev);
-  if (v == FCTN_OK && hipMemcpyAsync(S->pin_flag + slot, P->bad_flag, sizeof(int32_t),
+  if (v == FCTN_OK && hipMemcpyAsync(S->pin_flag + 2 * slot, P->bad_flag, sizeof(int32_t),
                                      hipMemcpyDeviceToHost, st) != hipSuccess)
     v = FCTN_E_DEVICE;
   if (v != FCTN_OK) {
@@ -1440,6 +1463,9 @@ fctn_status srv_finish(fctn_server_s* S, int slot) {
   fctn_plan_s* P = sl.plan;
   if (hipMemcpyAsync(sl.req.X_out_dev, P->X, P->numel * P->es, hipMemcpyDeviceToDevice,
                      P->st) != hipSuccess)
+    return FCTN_E_DEVICE;
+  if (hipMemcpyAsync(S->pin_flag + 2 * slot + 1, P->dev_err, sizeof(int32_t),
+                     hipMemcpyDeviceToHost, P->st) != hipSuccess)
     return FCTN_E_DEVICE;
   double* ps = S->pin_stats + 4 * slot;
   if (P->sweeps_done > 0) {
@@ -1475,7 +1501,7 @@ fctn_status fctn_server_create(void* arena_dev, size_t arena_bytes, void* const*
   for (int i = 0; i < nstreams; ++i) S->streams.push_back((hipStream_t)streams[i]);
   S->depth = depth;
   S->slots.resize(max_active);
-  if (hipHostMalloc((void**)&S->pin_flag, sizeof(int32_t) * max_active, hipHostMallocDefault) !=
+  if (hipHostMalloc((void**)&S->pin_flag, sizeof(int32_t) * 2 * max_active, hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void**)&S->pin_stats, sizeof(double) * 4 * max_active,
                     hipHostMallocDefault) != hipSuccess) {
@@ -1516,7 +1542,8 @@ fctn_status fctn_server_step(fctn_server_t S, fctn_completion* done, int32_t max
     if (q != hipSuccess) return srv_fail(S, FCTN_E_DEVICE);
     fctn_completion& c = done[(*n_done)++];
     c.tag = sl.req.tag;
-    c.status = S->pin_flag[i] ? FCTN_E_NUMERIC : FCTN_OK;
+    c.status = S->pin_flag[2 * i + 1] ? FCTN_E_DEVICE
+               : S->pin_flag[2 * i] ? FCTN_E_NUMERIC : FCTN_OK;
     c.sweeps_done = sl.enq;
     c.rel_change = S->pin_stats[4 * i + 0];
     c.objective = S->pin_stats[4 * i + 3];

@@ -71,7 +71,8 @@ template <int SB>
 __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict__ G, int Ik,
                                                         int s, double lam, double delta,
                                                         double rho, double* __restrict__ At,
-                                                        double* __restrict__ trace_part) {
+                                                        double* __restrict__ trace_part,
+                                                        int32_t* __restrict__ err) {
   constexpr int LDP = 32 * SB;
   extern __shared__ double smem[];
   double* const pan0 = smem;
@@ -267,6 +268,9 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
             avail = __hip_atomic_load(pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (avail <= j) __builtin_amdgcn_s_sleep(1);
           }
+          // bound reached: the result is invalid; flag it for the host, which
+          // reports FCTN_E_DEVICE at its next read of results
+          if (avail <= j) *err = 1;
           const int gj = j >> 3, cj = j & 7;
           const double sc = g == gj ? rdiag[p0 + j] : 1.0;
           xa[cj] *= sc;
@@ -439,7 +443,7 @@ __global__ void __launch_bounds__(1024) solve_classes_k(const double* __restrict
 
 hipError_t launch_solve_classes(const double* G, int32_t Ik, int32_t s, double lam,
                                 double delta, double rho, double* At, double* trace_part,
-                                hipStream_t st) {
+                                int32_t* err, hipStream_t st) {
   const int ncls = Ik / 2 + 1;
   const int sb = (s + 31) / 32;
   const size_t lds = solve_lds_doubles(sb) * sizeof(double);
@@ -449,7 +453,7 @@ hipError_t launch_solve_classes(const double* G, int32_t Ik, int32_t s, double l
     hipFuncSetAttribute((const void*)solve_classes_k<N>,                                   \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);             \
     solve_classes_k<N><<<ncls, 1024, lds, st>>>(G, Ik, s, lam, delta, rho, At,           \
-                                                trace_part);                               \
+                                                trace_part, err);                          \
     break;
     FCTN_SOLVE_CASE(1)
     FCTN_SOLVE_CASE(2)

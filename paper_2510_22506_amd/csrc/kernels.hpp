@@ -142,9 +142,10 @@ hipError_t launch_reduce_gb(int prec, const GramGeom& g, const void* part, const
                             int64_t spost, double rho, double* G, double* B, hipStream_t st);
 hipError_t launch_project(const double* Qt, const double* B, int32_t Ik, int32_t s, double* Bt,
                           hipStream_t st);
+// err: set to 1 if a class's bounded wait gave up (the result is then invalid)
 hipError_t launch_solve_classes(const double* G, int32_t Ik, int32_t s, double lam,
                                 double delta, double rho, double* At, double* trace_part,
-                                hipStream_t st);
+                                int32_t* err, hipStream_t st);
 // A_k = fold(Q a~) into A64 (float64 master), Aw (working precision, factor
 // layout) and Au (working precision, mode-k unfolding).  alpha > 0 applies the
 // asymmetric extrapolation A <- (1 + alpha) A - alpha beta A64_old elementwise,

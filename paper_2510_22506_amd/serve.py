@@ -30,13 +30,21 @@ def run(server, requests, arrivals=None):
         while nxt < n and arr[order[nxt]] <= now:
             server.submit(**requests[order[nxt]])
             nxt += 1
-        for c, X in server.step():
+        fresh = server.step()
+        for c, X in fresh:
             done[c["tag"]] = (c, X)
-        if nxt < n and not done and server.query()[:2] == (0, 0):
-            # idle until the next arrival
-            wait = arr[order[nxt]] - (time.monotonic() - t0)
-            if wait > 0:
-                time.sleep(min(wait, 1e-3))
+        if fresh:
+            continue
+        if server.query()[:2] == (0, 0):
+            # nothing resident or queued: idle until the next arrival
+            if nxt < n:
+                wait = arr[order[nxt]] - (time.monotonic() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 1e-3))
+        else:
+            # work in flight and nothing finished: yield the host core briefly
+            # instead of polling the completion events in a tight loop
+            time.sleep(5e-5)
     wall = max(c["t_done"] for c, _ in done.values()) - (t0 + float(arr.min()))
     lat = {}
     for i, r in enumerate(requests):

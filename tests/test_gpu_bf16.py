@@ -4,13 +4,17 @@ split bf16 = hi*hi + hi*lo + lo*hi) against the FP64 oracle.
 Step level: the Gram and right-hand side of eq. 5 with bf16 operands are
 within the bf16 rounding bound of the oracle (2^-8 relative per operand,
 accumulated in fp32/fp64), split bf16 (about 16 mantissa bits per operand,
-2^-17 relative) within 2e-5.  Whole completions: the PSNR of the completion
-is within 0.05 dB of the oracle's for both forms.  Split bf16 meets the 1e-3
-relative-error bound of the benchmark specification for bf16 (measured
-~6e-5; asserted <= 2e-4: 2^-17 per operand amplified over the sweeps).
-Plain bf16 does not: rounding every Gram/RHS operand to 8 bits leaves it at
-~4e-3 after 20 sweeps; it is asserted against that measured level (1e-2).
+2^-17 relative) within 2e-5; both as a relative Frobenius norm and as the
+largest entry error over the largest oracle magnitude.  Whole completions:
+the PSNR of the completion is within 0.05 dB of the oracle's for both forms,
+and the relative error is held to the 1e-3 bound of the bf16 form.  Split
+bf16 meets it (measured ~6e-5).  Plain bf16 does not: rounding every
+Gram/RHS operand to 8 bits leaves it at ~4e-3 after 15-20 sweeps, so that
+case is reported as an expected failure with its measured error; its PSNR
+bound is still asserted.
 """
+
+import functools
 
 import numpy as np
 import pytest
@@ -30,6 +34,12 @@ def _rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _max_rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
 def _c_order(mat, lead, bonds):
@@ -54,29 +64,42 @@ def test_gram_rhs_step_bf16(prec, tol, dims, ranks):
         Go = _c_order(M @ M.T, bonds, bonds)
         Bo = _c_order(tensor.unfold(X.astype(np.float64), k) @ M.T + 0.1 * tensor.unfold(A[k], k),
                       [dims[k]], bonds)
-        assert _rel(G.cpu().numpy(), Go) <= tol, (k, _rel(G.cpu().numpy(), Go))
-        assert _rel(B.cpu().numpy(), Bo) <= tol, (k, _rel(B.cpu().numpy(), Bo))
+        Gg, Bg = G.cpu().numpy(), B.cpu().numpy()
+        assert _rel(Gg, Go) <= tol, (k, _rel(Gg, Go))
+        assert _rel(Bg, Bo) <= tol, (k, _rel(Bg, Bo))
+        assert _max_rel(Gg, Go) <= tol, (k, _max_rel(Gg, Go))
+        assert _max_rel(Bg, Bo) <= tol, (k, _max_rel(Bg, Bo))
 
 
-@pytest.mark.parametrize("name,dims,sweeps", [
-    ("c2", (64, 48, 3), 20), ("c3", (24, 28, 3, 6), 15), ("c4", (40, 36, 31), 15)])
-def test_sweeps_bf16_forms(name, dims, sweeps):
+@functools.lru_cache(maxsize=1)
+def _oracle(name, dims, sweeps):
     prob = make_problem(name, seed=6, dims=dims, precision="f32", sr=0.2)
     A0 = [a.astype(np.float32).astype(np.float64) for a in prob.A0]
     Xo, _, _ = pam.complete(prob.Y.astype(np.float64), prob.mask != 0, prob.ranks, prob.lam,
                             prob.delta, prob.rho, sweeps, A0, reuse=True, order_policy=1)
+    return Xo
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("name,dims,sweeps", [
+    ("c2", (64, 48, 3), 20), ("c3", (24, 28, 3, 6), 15), ("c4", (40, 36, 31), 15)])
+def test_sweeps_bf16_forms(name, dims, sweeps, prec):
+    prob = make_problem(name, seed=6, dims=dims, precision="f32", sr=0.2)
+    Xo = _oracle(name, dims, sweeps)
     psnr_o = metrics.psnr(prob.truth, Xo)
     obs = prob.mask != 0
-    for prec in ("bf16x3", "bf16"):
-        p = _plan(prob.dims, prob.ranks, prec, lam=prob.lam, delta=prob.delta, rho=prob.rho,
-                  reuse=True, order_policy=1)
-        p.set_factors(prob.A0)
-        p.set_observed(prob.Y, prob.mask)
-        p.sweep(sweeps)
-        Xg = p.x().cpu().numpy()
-        np.testing.assert_array_equal(Xg[obs], prob.Y[obs])
-        err = _rel(Xg, Xo)
-        dpsnr = abs(metrics.psnr(prob.truth, Xg) - psnr_o)
-        print(f"{name} {dims} {prec}: rel err {err:.3e}, |dPSNR| {dpsnr:.4f} dB")
-        assert dpsnr <= 0.05, (prec, err, dpsnr)
-        assert err <= (2e-4 if prec == "bf16x3" else 1e-2), (prec, err)
+    p = _plan(prob.dims, prob.ranks, prec, lam=prob.lam, delta=prob.delta, rho=prob.rho,
+              reuse=True, order_policy=1)
+    p.set_factors(prob.A0)
+    p.set_observed(prob.Y, prob.mask)
+    p.sweep(sweeps)
+    Xg = p.x().cpu().numpy()
+    np.testing.assert_array_equal(Xg[obs], prob.Y[obs])
+    err = _rel(Xg, Xo)
+    dpsnr = abs(metrics.psnr(prob.truth, Xg) - psnr_o)
+    print(f"{name} {dims} {prec}: rel err {err:.3e}, |dPSNR| {dpsnr:.4f} dB")
+    assert dpsnr <= 0.05, (prec, err, dpsnr)
+    if prec == "bf16" and err > 1e-3:
+        pytest.xfail(f"plain bf16 misses the 1e-3 bound: relative error {err:.2e} "
+                     "(8-bit Gram/RHS operands)")
+    assert err <= 1e-3, (prec, err)

@@ -102,6 +102,46 @@ def test_reuse_on_equals_off(dims, ranks, policy):
         assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(a)
 
 
+@pytest.mark.parametrize("dims,ranks", [
+    ((4, 5, 3), (2, 3, 2)),
+    ((3, 4, 2, 3), (2, 1, 2, 3, 2, 2)),
+    ((3, 2, 3, 2, 2), (2, 1, 2, 2, 2, 1, 2, 2, 1, 2)),
+])
+def test_loop_subnetwork_equals_property1_unfolding(dims, ranks):
+    # the PAM loop's M_k (pair-cache route for N = 4 with reuse, factor chain
+    # otherwise) against tensor.subnetwork_unfolded, itself pinned to the
+    # brute-force index sum; then, after a factor changes, the cache must hand
+    # out the M_k of the new factors (version bump) and keep the old ones
+    # while no version moves
+    rng = np.random.default_rng(3)
+    fs = init_factors(rng, dims, ranks)
+    N = len(dims)
+    for reuse in (False, True):
+        cache = pam.PairCache()
+        versions = [0] * N
+        for k in range(N):
+            M = pam.subnetwork_M(fs, k, reuse, cache, versions, None)
+            Mo = tensor.subnetwork_unfolded(fs, k)
+            assert M.shape == Mo.shape
+            assert np.max(np.abs(M - Mo)) <= 1e-12 * np.max(np.abs(Mo)), (reuse, k)
+        changed = [f.copy() for f in fs]
+        j = N - 1
+        changed[j] = rng.standard_normal(fs[j].shape)
+        k = 0
+        stale = pam.subnetwork_M(changed, k, reuse, cache, versions, None)
+        fresh_versions = list(versions)
+        fresh_versions[j] += 1
+        fresh = pam.subnetwork_M(changed, k, reuse, cache, fresh_versions, None)
+        Mo_new = tensor.subnetwork_unfolded(changed, k)
+        assert np.max(np.abs(fresh - Mo_new)) <= 1e-12 * np.max(np.abs(Mo_new))
+        if reuse and N == 4:
+            # pair (3, 4) cached from the old factors: still the old M_1
+            Mo_old = tensor.subnetwork_unfolded(fs, k)
+            assert np.max(np.abs(stale - Mo_old)) <= 1e-12 * np.max(np.abs(Mo_old))
+        else:
+            assert np.max(np.abs(stale - Mo_new)) <= 1e-12 * np.max(np.abs(Mo_new))
+
+
 def test_order2_full_observation_reaches_eckart_young():
     # N = 2, every entry observed, lambda = 0: PAM on ||X - A1 A2||^2 converges
     # to the best rank-R approximation, whose error is the tail singular values
