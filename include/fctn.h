@@ -168,6 +168,21 @@ fctn_status fctn_regrow(fctn_plan_t to, fctn_plan_t from, const double* fill_dev
 fctn_status fctn_sweep(fctn_plan_t plan, int32_t nsweeps,
                        fctn_sweep_stats* stats_host);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same `nsweeps` sweeps as fctn_sweep (results bit for bit equal), with the
+ * split-K partial products of the Gram/right-hand-side pass (eq. 5) kept in
+ * a static device array owned by the library (64 MiB, allocated on each
+ * device when the library's code is loaded there and held until the process
+ * ends) instead of the plan's workspace.  Calls nothing that allocates.
+ * Returns FCTN_E_NOMEM if the plan's partial products exceed 64 MiB (e.g.
+ * float64 plans of large tensors; fctn_sweep serves those).  Every plan on
+ * one device shares that array: calls of this entry point that overlap in
+ * time on one device (plans on different streams, or different threads)
+ * race and must be serialized by the caller.  No stats: read them with
+ * fctn_get_history. */
+fctn_status fctn_sweep_noalloc(fctn_plan_t plan, int32_t nsweeps);
+
 /* Run `nsweeps` sweeps on each of `count` independent plans, interleaving
  * their launches across the plans' streams so that their work overlaps on the
  * device (request batching).  Each plan's results equal those of fctn_sweep

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -90,12 +91,15 @@ struct fctn_plan_s {
   int64_t pnum[2];
   PairDesc pd[2];
   void* part;
+  void* part_cur;    // where this call's split-K partials go: part, or the
+                     // static scratch array (fctn_sweep_noalloc)
   double *G, *B, *At;
   double* Q[FCTN_MAX_ORDER];
   double* Qt[FCTN_MAX_ORDER];
   double* lamcol[FCTN_MAX_ORDER];
   double* trace_part;
   int max_cls;
+  size_t part_bytes;  // size of the split-K partial region
   double* lam_half;
   int32_t* ncls_dev;
   double* xpart;
@@ -589,6 +593,8 @@ size_t carve(fctn_plan_s* P, char* base) {
   for (int p = 0; p < 2; ++p) P->P[p] = (N == 4) ? c.take(P->pnum[p] * es) : nullptr;
   for (int r = 0; r < 2; ++r) P->Gb[r] = P->gnum[r] > 0 ? c.take(P->gnum[r] * es) : nullptr;
   P->part = c.take(part_bytes);
+  P->part_cur = P->part;
+  P->part_bytes = part_bytes;
   P->G = (double*)c.take(smax * smax * sizeof(double));
   P->B = (double*)c.take(imax * smax * sizeof(double));
   P->At = (double*)c.take(imax * smax * sizeof(double));
@@ -758,10 +764,10 @@ fctn_status gram_rhs(fctn_plan_s* P, int k, double* G, double* B) {
   const double part_bytes = (double)m.geom.nSplit * m.geom.nTiles * 256 * acc_es;
   FCTN_TIMED(P, FCTN_STAGE_GRAM_RHS, 2.0 * sC * (m.mg.K + m.s + m.Ik),
              (double)P->numel * P->es + part_bytes,
-             launch_gram_rhs(P->prec, g, P->X, m.xv, m.geom, P->part, P->st));
+             launch_gram_rhs(P->prec, g, P->X, m.xv, m.geom, P->part_cur, P->st));
   FCTN_TIMED(P, FCTN_STAGE_REDUCE, (double)m.geom.nSplit * (m.s * m.s + m.Ik * m.s),
              part_bytes + 8.0 * (m.s * m.s + 2 * m.Ik * m.s),
-             launch_reduce_gb(P->prec, m.geom, P->part, P->A64[k], m.spost, P->d.rho, G, B,
+             launch_reduce_gb(P->prec, m.geom, P->part_cur, P->A64[k], m.spost, P->d.rho, G, B,
                               P->st));
   return FCTN_OK;
 }
@@ -1111,6 +1117,65 @@ fctn_status fctn_sweep(fctn_plan_t P, int32_t nsweeps, fctn_sweep_stats* stats_h
     return read_slot(P, P->hist + ((P->sweeps_done - 1) % kHist) * 4, stats_host);
   }
   return FCTN_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The split-K partial products of fctn_sweep_noalloc live in this array
+// instead of the plan's workspace.  In host code `scratch` only names the
+// symbol: its device address, one per device, comes from
+// hipGetSymbolAddress and is what kernels receive.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device of `st` (looked up once per
+// device, with that device current; the caller's current device is restored).
+fctn_status static_scratch(hipStream_t st, void** out) {
+  int dev = 0;
+  if (hipStreamGetDevice(st, &dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return FCTN_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return FCTN_E_DEVICE;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return FCTN_E_DEVICE;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) return FCTN_E_DEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FCTN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fctn_status fctn_sweep_noalloc(fctn_plan_t P, int32_t nsweeps) {
+  if (!P || nsweeps < 0) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  if (P->part_bytes > kStaticScratchBytes) return FCTN_E_NOMEM;
+  void* ptr = nullptr;
+  fctn_status v = static_scratch(P->st, &ptr);
+  if (v != FCTN_OK) return v;
+  // every partial tile is written by the Gram pass before the reduction reads
+  // it, so nothing in the array needs clearing
+  // per-kernel timing records events into growing host lists: off here
+  const bool prof = P->prof_on;
+  P->prof_on = false;
+  P->part_cur = ptr;
+  for (int32_t i = 0; i < nsweeps && v == FCTN_OK; ++i) v = one_sweep(P);
+  P->part_cur = P->part;
+  P->prof_on = prof;
+  return v;
 }
 
 fctn_status fctn_sweep_many(fctn_plan_t* plans, int32_t count, int32_t nsweeps) {

@@ -99,6 +99,7 @@ _SIGS = {
     "fctn_regrow": (ctypes.c_int, [_P, _P, _P]),
     "fctn_sweep": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(fctn_sweep_stats)]),
     "fctn_sweep_many": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32]),
+    "fctn_sweep_noalloc": (ctypes.c_int, [_P, ctypes.c_int32]),
     "fctn_complete": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
                                      ctypes.POINTER(fctn_stats)]),
     "fctn_get_history": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32,
@@ -264,6 +265,11 @@ class Plan:
         _check(lib().fctn_sweep(self.handle, int(n), ctypes.byref(st) if stats else None),
                "fctn_sweep")
         return st.as_dict() if stats else None
+
+    def sweep_noalloc(self, n=1):
+        """fctn_sweep_noalloc: the sweeps with the split-K partials in the
+        library's static device array."""
+        _check(lib().fctn_sweep_noalloc(self.handle, int(n)), "fctn_sweep_noalloc")
 
     def complete(self, max_sweeps, tol=0.0, check_every=1, X_out=None):
         st = fctn_stats()
