@@ -265,14 +265,15 @@ def rank_schedule(prob, prec, ext, sweeps=20):
                           "from": list(below), "to": list(rmax)}}
 
 
-def other_workload(name, steps=40, warmup=3):
-    """Sweeps/s of another configuration (default precision, reuse on), timed
-    like the main one, with its dominant kernel's roofline from an
-    event-bracketed pass."""
+def other_workload(spec, steps=40, warmup=3):
+    """Sweeps/s of another configuration, `name` or `name:precision` (default
+    precision otherwise; reuse on), timed like the main one, with its
+    dominant kernel's roofline from an event-bracketed pass."""
     import torch
     from paper_2510_22506_amd import Plan
     from workloads import make_problem
-    prec = DEFAULT_PREC[name]
+    name, _, prec = spec.partition(":")
+    prec = prec or DEFAULT_PREC[name]
     prob = make_problem(name, seed=0, precision=("f64" if prec == "f64" else "f32"))
     plan = Plan(prob.dims, prob.ranks, prob.lam, prob.delta, prob.rho, precision=prec,
                 device="cuda:0", extrapolation=DEFAULT_EXTRAP.get(name))
@@ -297,7 +298,49 @@ def other_workload(name, steps=40, warmup=3):
             "roofline": roofs[dom]}
 
 
-def cpu_baseline(prob, sweeps, ext=None):
+def time_variant(prob, prec, ext, steps, warmup, reuse=True):
+    """Sweeps/s of the workload in another form (precision, reuse switch),
+    timed like the main measurement (no events), with the pair-tensor
+    launches per sweep from a second, event-bracketed pass."""
+    import torch
+    from paper_2510_22506_amd import Plan
+    plan = Plan(prob.dims, prob.ranks, prob.lam, prob.delta, prob.rho, precision=prec,
+                reuse=reuse, order_policy=1, device="cuda:0", extrapolation=ext)
+    plan.set_factors(prob.A0)
+    plan.set_observed(torch.from_numpy(prob.Y), torch.from_numpy(prob.mask))
+    plan.sweep(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.sweep(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.profile_enable(True)
+    plan.profile_read(reset=True)
+    plan.sweep(steps)
+    prof = plan.profile_read(reset=True)
+    plan.close()
+    return {"precision": prec, "reuse": reuse, "value": steps / dt, "unit": "sweeps/s",
+            "ms_per_step": dt / steps * 1e3,
+            "pair_launches_per_sweep": prof["pair"]["launches"] / steps,
+            "contraction_gflop_per_sweep":
+                sum(prof[k]["flops"] for k in CONTRACTION_STAGES) / steps / 1e9}
+
+
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(prob, sweeps, ext=None, runs=3):
+    """The float64 oracle on the host cores: the median over `runs` runs of
+    `sweeps` sweeps each from the same initial factors (rate in sweeps/s)."""
     import numpy as np
     from threadpoolctl import threadpool_info
     from oracle import pam
@@ -305,14 +348,20 @@ def cpu_baseline(prob, sweeps, ext=None):
     if prob.precision != "f64":
         A0 = [a.astype(np.float32).astype(np.float64) for a in A0]
     Y = prob.Y.astype(np.float64)
-    t0 = time.perf_counter()
-    pam.complete(Y, prob.mask != 0, prob.ranks, prob.lam, prob.delta, prob.rho, sweeps, A0,
-                 reuse=True, order_policy=1, extrapolation=ext)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        pam.complete(Y, prob.mask != 0, prob.ranks, prob.lam, prob.delta, prob.rho, sweeps, A0,
+                     reuse=True, order_policy=1, extrapolation=ext)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return {"value": sweeps / dt, "unit": "sweeps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{sweeps} sweeps of the same workload from the same initial factors "
-                      f"({dt:.1f} s, float64 NumPy, {os.cpu_count()} host CPUs visible)"}
+            "cpu": cpu_model(),
+            "sample": f"median of {runs} runs of {sweeps} sweeps of the same workload from the "
+                      f"same initial factors (run times "
+                      f"{', '.join(f'{t:.1f}' for t in times)} s; float64 NumPy; "
+                      f"{os.cpu_count()} host CPUs visible)"}
 
 
 def main():
@@ -327,15 +376,18 @@ def main():
                     help="alpha,beta of the asymmetric extrapolation, or 'off' "
                          "(default: on at 0.5,0.5 for c6, off otherwise)")
     ap.add_argument("--order-policy", type=int, default=1)
-    ap.add_argument("--cpu-sweeps", type=int, default=14)
+    ap.add_argument("--cpu-sweeps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="add the per-stage breakdown")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the reuse-off and bf16-form rates of the same workload")
     ap.add_argument("--no-rank-schedule", action="store_true",
                     help="skip the rank-increasing schedule measurement")
-    ap.add_argument("--also", default="c2",
-                    help="comma-separated other workloads reported under 'other_workloads' "
-                         "('' for none; default: the 256x256x3 image)")
+    ap.add_argument("--also", default="c2,c4,c4:bf16x3",
+                    help="comma-separated other workloads (name or name:precision) reported "
+                         "under 'other_workloads' ('' for none; default: the 256x256x3 image "
+                         "and the 512x512x31 multispectral tensor in float32 and split bf16)")
     ap.add_argument("--no-xpass-large", action="store_true",
                     help="skip the X/mask pass on a 1 GiB tensor")
     ap.add_argument("--serve-n", type=int, default=256)
@@ -435,6 +487,15 @@ def main():
                               "us_per_launch": v["ms"] * 1e3 / max(v["launches"], 1),
                               "gflop": v["flops"] / 1e9, "roofline": roofs[k]}
                           for k, v in prof.items() if v["launches"]}
+    if not args.no_variants:
+        # Table 1's reuse mechanism measured: the same sweeps with reuse off
+        # (every sub-network and FCTN(A) contracted from the factors); and the
+        # other precision forms of the same workload
+        line["reuse_off"] = time_variant(prob, prec, ext, args.steps, args.warmup, reuse=False)
+        line["reuse_off"]["speedup_reuse_on"] = value / line["reuse_off"]["value"]
+        if prec == "f32":
+            line["forms"] = {f: time_variant(prob, f, ext, args.steps, args.warmup)
+                             for f in ("bf16x3", "bf16")}
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
@@ -447,7 +508,7 @@ def main():
             line["roofline_xpass_large"] = xpass_large()
         except Exception as e:  # reported, never hides the sweep measurement
             line["roofline_xpass_large"] = {"error": f"{type(e).__name__}: {e}"}
-    others = [w for w in args.also.split(",") if w and w != name]
+    others = [w for w in args.also.split(",") if w and w != name and w != f"{name}:{prec}"]
     if others:
         line["other_workloads"] = {}
         for w in others:

@@ -377,6 +377,13 @@ bool setup_modes(fctn_plan_s* P) {
 }
 
 inline int ld_mod(int x, int r) { return x + ((r - x % 64) % 64 + 64) % 64; }
+// Slab row strides for the generator's MFMA operand reads (lane = 16 rows x
+// 4 k): [p][kap] rows (lanes read row p0 + l%16 at kap k0 + l/16) need a
+// stride that is 4 times an odd number; [kap][p] rows (lanes read row
+// k0 + l/16 at p0 + l%16) a stride of 16 mod 32.  Either way the 64 lanes of
+// one read hit 64 distinct banks.
+inline int ld_pk(int kp) { return kp + ((4 - kp % 8) % 8 + 8) % 8; }
+inline int ld_kp(int pp) { return pp + ((16 - pp % 32) % 32 + 32) % 32; }
 inline int floor_log2(int x) {
   int l = 0;
   while ((2 << l) <= x) ++l;
@@ -397,14 +404,14 @@ void fill_tile(const MGen& mg, int TCu, int TCv, int kalign, TileGeom* tg) {
   tg->Qp = pad16(tg->Qv);
   tg->Kp = (mg.K + 3) / 4 * 4;
   if (mg.u_k == 1 && mg.K > 1) {
-    tg->us_k = 1; tg->us_p = ld_mod(tg->Kp, 4); tg->u_len = tg->Pp * tg->us_p;
+    tg->us_k = 1; tg->us_p = ld_pk(tg->Kp); tg->u_len = tg->Pp * tg->us_p;
   } else {
-    tg->us_p = 1; tg->us_k = ld_mod(tg->Pp, 16); tg->u_len = tg->Kp * tg->us_k;
+    tg->us_p = 1; tg->us_k = ld_kp(tg->Pp); tg->u_len = tg->Kp * tg->us_k;
   }
   if (mg.v_k == 1 && mg.K > 1) {
-    tg->vs_k = 1; tg->vs_q = ld_mod(tg->Kp, 4); tg->v_len = tg->Qp * tg->vs_q;
+    tg->vs_k = 1; tg->vs_q = ld_pk(tg->Kp); tg->v_len = tg->Qp * tg->vs_q;
   } else {
-    tg->vs_q = 1; tg->vs_k = ld_mod(tg->Qp, 16); tg->v_len = tg->Kp * tg->vs_k;
+    tg->vs_q = 1; tg->vs_k = ld_kp(tg->Qp); tg->v_len = tg->Kp * tg->vs_k;
   }
   // staging lanes along the slab's contiguous index (at most 64)
   tg->u_lw = floor_log2(std::min(tg->us_k == 1 ? tg->Kp : tg->Pp, 64));
@@ -432,7 +439,7 @@ inline size_t table_bytes(const TileGeom& tg, bool with_cols) {
 
 template <class Extra, class Lds>
 bool choose_tile(const MGen& mg, int mg_repeat, int kalign, Extra extra_mfma, Lds lds,
-                 TileGeom* best) {
+                 TileGeom* best, size_t lds_shared = 80 * 1024) {
   static const int cv_c[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20, 24, 25, 30, 32, 40, 48, 50, 64};
   static const int cu_c[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
   double best_cost = 1e300;
@@ -464,7 +471,7 @@ bool choose_tile(const MGen& mg, int mg_repeat, int kalign, Extra extra_mfma, Ld
       double cost = (mgen + stage + extra_mfma(tg) + 24.0) / real;
       // above 80 KB only one workgroup fits a CU, and none overlaps its
       // staging with another's MFMA work (measured: 1.3x-1.5x slower)
-      if (bytes > 80 * 1024) cost *= 1.5;
+      if (bytes > lds_shared) cost *= 1.5;
       const double par = (double)tg.nColTiles * mg_repeat;
       if (par < 512.0) cost *= 512.0 / std::max(par, 1.0);   // too few tiles to fill 256 CUs
       if (cost < best_cost * 0.999) {
@@ -491,6 +498,18 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
   g.nTiles = g.nG + g.nB;
   const int tpg = gram_tiles_per_group();
   g.tilesPerGroup = tpg;
+  // 16 waves of 8 tiles (one workgroup per CU, all of its LDS) or 8 waves of
+  // 16 tiles (two workgroups per CU); the same 128 tiles per group either way.
+  // The bf16 forms take the 16-wave form: their hi/lo tiles need LDS that
+  // would leave room for one 8-wave workgroup per CU, and the split form's
+  // 16-tile instance needs 243 registers (two waves per SIMD), its 8-tile
+  // instance 128 (four); measured on the 144x176x3x50 video shape, modes with
+  // s_k = 192: 104/96/158 us -> 73/63/107 us (split), 63/66/109 -> 57/50/86
+  // (plain).  float32 keeps two 8-wave workgroups (16 waves: 86/78/103 us
+  // against 81/84/122, and slower at s_k = 128).  Modes with at most 16
+  // output tiles run the small-tile instance (8 waves) in every form.
+  const bool small_tiles = g.nTiles <= 16;
+  g.nw = (prec == FCTN_BF16 || prec == FCTN_BF16X3) && !small_tiles ? 16 : 8;
   g.nGroups = (g.nTiles + tpg - 1) / tpg;
   int xmax = 0;
   for (int grp = 0; grp < g.nGroups; ++grp) {
@@ -518,7 +537,8 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
     return (double)g.nTiles * (tg.tcolp / 4);
   };
   // column tiles in whole 16-byte reads per lane group: 4 (16 / es) columns
-  if (!choose_tile(m.mg, g.nGroups, bf ? 32 : 64 / (int)es, gram_work, gram_lds, &g.tg))
+  if (!choose_tile(m.mg, g.nGroups, bf ? 32 : 64 / (int)es, gram_work, gram_lds, &g.tg,
+                   g.nw == 16 ? (size_t)gram_max_lds_bytes() : (size_t)80 * 1024))
     return false;
   if (bf) {
     g.ldm = g.tg.tcolp + 8;
@@ -527,7 +547,7 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
   }
   g.ldx = g.ldm;
   g.lds_bytes = gram_lds(g.tg);
-  int64_t ns = std::max<int64_t>(1, kTargetGramWGs / g.nGroups);
+  int64_t ns = std::max<int64_t>(1, (g.nw == 16 ? 256 : kTargetGramWGs) / g.nGroups);
   ns = std::min<int64_t>(ns, g.tg.nColTiles);
   g.colTilesPerSplit = (g.tg.nColTiles + ns - 1) / ns;
   g.nSplit = (int32_t)((g.tg.nColTiles + g.colTilesPerSplit - 1) / g.colTilesPerSplit);

@@ -258,8 +258,8 @@ __device__ inline void stage_operands(const MGen& mg, const TileGeom& tg, const 
 // and X staging keep kGatherBatch loads in flight per thread.  VEC: the
 // instance with 16-byte staging of [kap][p] slabs, kept separate because its
 // extra code raises the kernel's register spills.
-template <typename T, int TPW, bool VEC = false>
-__global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MGen mg, const T* __restrict__ X,
+template <typename T, int TPW, bool VEC = false, int NW = kGramWaves>
+__global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MGen mg, const T* __restrict__ X,
                                                            XView xv, GramGeom g,
                                                            T* __restrict__ part) {
   constexpr bool kBatch = TPW <= 4;
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
   typename MM::acc_t acc[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
-    const int t = t0 + wave + kGramWaves * j;
+    const int t = t0 + wave + NW * j;
     valid[j] = t < t1;
     acc[j] = MM::zero();
     int bi = 0, bj = 0;
@@ -322,11 +322,11 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
     tdesc[j] = (fx ? 1 : 0) | (bi << 1) | (bj << 11);
   }
 
-  build_tables(mg, tg, &xv, g.ldm, 1, ptab, qtab, ctab, tid, kGramThreads);
+  build_tables(mg, tg, &xv, g.ldm, 1, ptab, qtab, ctab, tid, (64 * NW));
   // rows of M beyond s and columns beyond the tile (in M and X) stay zero for
   // the whole launch: uninitialized LDS could hold NaN patterns, and NaN * 0
   // would poison the products
-  for (int e = tid; e < (g.sp + g.xrows) * g.ldm; e += kGramThreads) Ms[e] = T(0);
+  for (int e = tid; e < (g.sp + g.xrows) * g.ldm; e += (64 * NW)) Ms[e] = T(0);
   __syncthreads();
 
   const int64_t ct0 = (int64_t)split * g.colTilesPerSplit;
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
     stage_operands<T, kBatch, VEC>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
-                              kGramThreads);
+                              (64 * NW));
     FCTN_GRAM_MARK(0);
     if (xrows > 0) {
       const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
       const int xlim = xv.Ik - ba_lo * 16;
       if constexpr (kBatch) {
         // thread (c, r0): column c, rows r0, r0 + ngrp, ...
-        const int ngrp = kGramThreads / tg.tcol;
+        const int ngrp = (64 * NW) / tg.tcol;
         if (tid < ngrp * tg.tcol) {
           gather2d<T>(
               tid % tg.tcol, tg.tcol, tg.tcol, tid / tg.tcol, ngrp, xrows,
@@ -364,7 +364,7 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
               [&](int c, int r, T v) { Xs[r * ldx + c] = v; });
         }
       } else if (x_rfast) {
-        const int l = tid % xl, grp = tid / xl, ngrp = kGramThreads / xl;
+        const int l = tid % xl, grp = tid / xl, ngrp = (64 * NW) / xl;
         for (int c = grp; c < tg.tcol; c += ngrp) {
           const SlabRow cr = ctab[c];
           const bool okc = cr.cl < lim_u && cr.map < lim_v;
@@ -372,9 +372,9 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
             Xs[r * ldx + c] = (okc && r < xlim) ? xb[cr.off + (int64_t)r * xv.x_ik] : T(0);
         }
       } else {
-        // element e = tid + i * kGramThreads of the row-major (r, c) walk,
+        // element e = tid + i * (64 * NW) of the row-major (r, c) walk,
         // advanced without a division per element
-        const int dr = kGramThreads / tg.tcol, dc = kGramThreads - dr * tg.tcol;
+        const int dr = (64 * NW) / tg.tcol, dc = (64 * NW) - dr * tg.tcol;
         int r = tid / tg.tcol, c = tid - r * tg.tcol;
         while (r < xrows) {
           const SlabRow cr = ctab[c];
@@ -392,7 +392,7 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
     FCTN_GRAM_MARK(1);
     __syncthreads();
     FCTN_GRAM_MARK(2);
-    mgen_mfma<T>(tg, Us, Vs, ptab, qtab, Ms, lane, wave, kGramWaves);
+    mgen_mfma<T>(tg, Us, Vs, ptab, qtab, Ms, lane, wave, NW);
     FCTN_GRAM_MARK(3);
     __syncthreads();
     FCTN_GRAM_MARK(4);
@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(kGramThreads, sizeof(T) == 4 ? 4 : 1) gram_rhs
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     if (valid[j]) {
-      const int t = t0 + wave + kGramWaves * j;
+      const int t = t0 + wave + NW * j;
       T* base = part + ((int64_t)split * g.nTiles + t) * 256;
 #pragma unroll
       for (int i = 0; i < 4; ++i) base[MM::row(lane, i) * 16 + (lane & 15)] = acc[j][i];
@@ -449,8 +449,8 @@ int gram_tiles_per_group() { return kGramWaves * kTPW; }
 // bf16: at most 128 VGPRs (two workgroups per CU, as for float32); the split
 // form keeps the default budget (its tiles need more than half a CU's LDS,
 // so it runs one workgroup per CU anyway)
-template <int X3, int TPW>
-__global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen mg, const float* __restrict__ X,
+template <int X3, int TPW, int NW = kGramWaves>
+__global__ void __launch_bounds__(64 * NW, (X3 && NW == NW) ? 1 : 4) gram_rhs_bf16_k(MGen mg, const float* __restrict__ X,
                                                                 XView xv, GramGeom g,
                                                                 float* __restrict__ part) {
   typedef Mfma<float> MF;
@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
   MF::acc_t acc[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
-    const int t = t0 + wave + kGramWaves * j;
+    const int t = t0 + wave + NW * j;
     valid[j] = t < t1;
     acc[j] = MF::zero();
     int bi = 0, bj = 0;
@@ -510,12 +510,12 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
   }
   const int loff = (lane & 15) * ldb + 8 * (lane >> 4);
 
-  build_tables(mg, tg, &xv, ldb, 1, ptab, qtab, ctab, tid, kGramThreads);
+  build_tables(mg, tg, &xv, ldb, 1, ptab, qtab, ctab, tid, (64 * NW));
   {
     // M tile(s) then X tile(s), hi and (X3) lo copies: every padding column
     // must read as zero
     const int nzero = (g.sp + g.xrows) * ldb * (1 + X3);
-    for (int e = tid; e < nzero; e += kGramThreads) Mh[e] = 0;
+    for (int e = tid; e < nzero; e += (64 * NW)) Mh[e] = 0;
   }
   __syncthreads();
 
@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
     stage_operands<float, true>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
-                                kGramThreads);
+                                (64 * NW));
     if (xrows > 0) {
       const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
       const int64_t lim_u = mg.Cu - cu0, lim_v = mg.Cv - cv0;
@@ -546,13 +546,13 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
       };
       if (x_rfast) {
         const int xl = min(xrows, 16);
-        const int l = tid % xl, grp = tid / xl, ngrp = kGramThreads / xl;
+        const int l = tid % xl, grp = tid / xl, ngrp = (64 * NW) / xl;
         gather2d<float>(
             l, xl, xrows, grp, ngrp, tg.tcol, xsrc,
             [&](int r, int c, float v) { put(Xh, Xl, r * ldb + c, v); });
       } else {
         gather2d<float>(
-            lane, 64, tg.tcol, wave, kGramWaves, xrows,
+            lane, 64, tg.tcol, wave, NW, xrows,
             [&](int c, int r) { return xsrc(r, c); },
             [&](int c, int r, float v) { put(Xh, Xl, r * ldb + c, v); });
       }
@@ -560,7 +560,7 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
     __syncthreads();
     mgen_mfma_store<float>(tg, Us, Vs, ptab, qtab,
                            [&](int idx, float v) { put(Mh, Ml, idx, v); }, lane, wave,
-                           kGramWaves);
+                           NW);
     __syncthreads();
     for (int kk = 0; kk < tg.tcolp; kk += 32) {
 #pragma unroll
@@ -591,7 +591,7 @@ __global__ void __launch_bounds__(kGramThreads, X3 ? 1 : 4) gram_rhs_bf16_k(MGen
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     if (valid[j]) {
-      const int t = t0 + wave + kGramWaves * j;
+      const int t = t0 + wave + NW * j;
       float* base = part + ((int64_t)split * g.nTiles + t) * 256;
 #pragma unroll
       for (int i = 0; i < 4; ++i) base[MfmaBf16::row(lane, i) * 16 + (lane & 15)] = acc[j][i];
@@ -615,25 +615,35 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
     gram_rhs_k<double, kTPW><<<grid, kGramThreads, g.lds_bytes, st>>>(mg, (const double*)X, xv,
                                                                       g, (double*)part);
   } else {
-    // float32 data: one kernel instance per (precision form, tile variant)
-    auto run = [&](auto kern) {
+    // float32 data: one kernel instance per (precision form, tile variant,
+    // workgroup size)
+    auto run = [&](auto kern, int threads) {
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)g.lds_bytes);
-      hipLaunchKernelGGL(kern, grid, dim3(kGramThreads), g.lds_bytes, st, mg, (const float*)X,
-                         xv, g, (float*)part);
+      hipLaunchKernelGGL(kern, grid, dim3(threads), g.lds_bytes, st, mg, (const float*)X, xv, g,
+                         (float*)part);
     };
-    if (prec == P_BF16)
-      run(small ? gram_rhs_bf16_k<0, 2> : gram_rhs_bf16_k<0, kTPW>);
-    else if (prec == P_BF16X3)
-      run(small ? gram_rhs_bf16_k<1, 2> : gram_rhs_bf16_k<1, kTPW>);
-    else if (small)
-      run(gram_rhs_k<float, 2>);
-    else if (g.tg.u_vec || g.tg.v_vec)
+    const bool wide = g.nw == 2 * kGramWaves;   // 16 waves, 8 tiles each
+    constexpr int W2 = 2 * kGramWaves, T2 = kTPW / 2;
+    if (prec == P_BF16) {
+      if (small) run(gram_rhs_bf16_k<0, 2>, kGramThreads);
+      else if (wide) run(gram_rhs_bf16_k<0, T2, W2>, 2 * kGramThreads);
+      else run(gram_rhs_bf16_k<0, kTPW>, kGramThreads);
+    } else if (prec == P_BF16X3) {
+      if (small) run(gram_rhs_bf16_k<1, 2>, kGramThreads);
+      else if (wide) run(gram_rhs_bf16_k<1, T2, W2>, 2 * kGramThreads);
+      else run(gram_rhs_bf16_k<1, kTPW>, kGramThreads);
+    } else if (small) {
+      run(gram_rhs_k<float, 2>, kGramThreads);
+    } else if (g.tg.u_vec || g.tg.v_vec) {
       // a separate instance, so that the 16-byte staging code does not cost
       // the other modes' kernel registers
-      run(gram_rhs_k<float, kTPW, true>);
-    else
-      run(gram_rhs_k<float, kTPW>);
+      if (wide) run(gram_rhs_k<float, T2, true, W2>, 2 * kGramThreads);
+      else run(gram_rhs_k<float, kTPW, true>, kGramThreads);
+    } else {
+      if (wide) run(gram_rhs_k<float, T2, false, W2>, 2 * kGramThreads);
+      else run(gram_rhs_k<float, kTPW>, kGramThreads);
+    }
   }
   return hipGetLastError();
 }

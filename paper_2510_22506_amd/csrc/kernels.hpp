@@ -62,6 +62,9 @@ struct GramGeom {
   int32_t nSplit;
   int32_t ldm, ldx, xrows;   // LDS leading dims and X rows held per group
   size_t lds_bytes;
+  int32_t nw;                // waves per workgroup: 8 (16 tiles each, two
+                             // workgroups per CU) or 16 (8 tiles each, one
+                             // workgroup per CU with all of its LDS)
 };
 
 // Launch geometry of the reconstruction Z_(k) = A_k(k) M_k.
