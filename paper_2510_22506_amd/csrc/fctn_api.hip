@@ -439,7 +439,7 @@ inline size_t table_bytes(const TileGeom& tg, bool with_cols) {
 
 template <class Extra, class Lds>
 bool choose_tile(const MGen& mg, int mg_repeat, int kalign, Extra extra_mfma, Lds lds,
-                 TileGeom* best, size_t lds_shared = 80 * 1024) {
+                 TileGeom* best, size_t lds_shared = 80 * 1024, double mgen_w = 1.0) {
   static const int cv_c[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20, 24, 25, 30, 32, 40, 48, 50, 64};
   static const int cu_c[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
   double best_cost = 1e300;
@@ -460,7 +460,7 @@ bool choose_tile(const MGen& mg, int mg_repeat, int kalign, Extra extra_mfma, Ld
       fill_tile(mg, TCu, TCv, kalign, &tg);
       const size_t bytes = lds(tg);
       if (bytes > (size_t)gram_max_lds_bytes()) continue;
-      const double mgen = (double)(tg.Pp / 16) * (tg.Qp / 16) * (tg.Kp / 4) * mg_repeat;
+      const double mgen = (double)(tg.Pp / 16) * (tg.Qp / 16) * (tg.Kp / 4) * mg_repeat * mgen_w;
       const double real = ((double)mg.Cu / tg.nTileU) * ((double)mg.Cv / tg.nTileV);
       // staging: the U slab is reloaded when the cu block changes, the V slab
       // when the cv block changes (tiles run cv-block fastest); an element
@@ -474,6 +474,10 @@ bool choose_tile(const MGen& mg, int mg_repeat, int kalign, Extra extra_mfma, Ld
       if (bytes > lds_shared) cost *= 1.5;
       const double par = (double)tg.nColTiles * mg_repeat;
       if (par < 512.0) cost *= 512.0 / std::max(par, 1.0);   // too few tiles to fill 256 CUs
+      // one workgroup per CU: whole tiles per CU, so the last round of the
+      // launch is full only if the tile count divides evenly
+      if (lds_shared > 80 * 1024 && par >= 256.0)
+        cost *= std::ceil(par / 256.0) / (par / 256.0);
       if (cost < best_cost * 0.999) {
         best_cost = cost;
         *best = tg;
@@ -522,10 +526,18 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
   g.xrows = xmax;
   // M and X tiles are [row][column]; bf16 rows are tcolp + 8 bf16 values long,
   // float32/float64 rows tcolp + 16 bytes (16-byte aligned after the slabs)
+  // bf16 forms with a contraction length of at least 24 generate the
+  // sub-network tile in split bf16 from bf16 head/tail slabs ([p][kap], kap
+  // padded to a multiple of 32, plus 8)
+  const int kp4 = (m.mg.K + 3) / 4 * 4;
+  g.mg16 = bf && kp4 >= 24 ? 1 : 0;
+  g.ldk = (kp4 + 31) / 32 * 32 + 8;
   auto gram_lds = [&](const TileGeom& tg) {
-    if (bf)
-      return (size_t)(tg.u_len + tg.v_len) * es + table_bytes(tg, true) +
-             (size_t)(g.sp + xmax) * (tg.tcolp + 8) * 2 * nbf;
+    if (bf) {
+      const size_t slabs = g.mg16 ? (size_t)(tg.Pp + tg.Qp) * g.ldk * 4
+                                  : (size_t)(tg.u_len + tg.v_len) * es;
+      return slabs + table_bytes(tg, true) + (size_t)(g.sp + xmax) * (tg.tcolp + 8) * 2 * nbf;
+    }
     const size_t slabs = (table_bytes(tg, true) + (size_t)(tg.u_len + tg.v_len) * es + 15) &
                          ~(size_t)15;
     return slabs + (size_t)(g.sp + xmax) * (tg.tcolp + 16 / es) * es;
@@ -537,8 +549,11 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
     return (double)g.nTiles * (tg.tcolp / 4);
   };
   // column tiles in whole 16-byte reads per lane group: 4 (16 / es) columns
+  // a split-bf16 generator step (three 16x16x32 MFMAs, about half an fp32
+  // 16x16x4 issue each) covers 32 kap against the float32 one's 4
   if (!choose_tile(m.mg, g.nGroups, bf ? 32 : 64 / (int)es, gram_work, gram_lds, &g.tg,
-                   g.nw == 16 ? (size_t)gram_max_lds_bytes() : (size_t)80 * 1024))
+                   g.nw == 16 ? (size_t)gram_max_lds_bytes() : (size_t)80 * 1024,
+                   g.mg16 ? 1.5 / 8.0 : 1.0))
     return false;
   if (bf) {
     g.ldm = g.tg.tcolp + 8;

@@ -438,6 +438,74 @@ int gram_threads() { return kGramThreads; }
 int gram_tiles_per_group() { return kGramWaves * kTPW; }
 
 // ---------------------------------------------------------------------------
+// Split-bf16 sub-network generation (bf16 forms, contraction length K >= 24).
+// The operand slabs are staged as bf16 heads and tails, row p holding kap
+// contiguously (row stride ldk, a multiple of 8 plus 8), whatever the slab's
+// order in HBM; each product is hi*hi + hi*lo + lo*hi on 16x16x32 bf16 MFMA
+// with fp32 accumulation (the dropped lo*lo term is about 2^-16 of the
+// product).
+// ---------------------------------------------------------------------------
+__device__ inline void stage_slab_bf16(const float* __restrict__ F, int64_t base, int64_t f_k,
+                                       int K, int Kp, int Pp, bool k_fast, int lw,
+                                       const SlabRow* __restrict__ tab, int64_t lim,
+                                       uint16_t* __restrict__ Sh, uint16_t* __restrict__ Sl,
+                                       int ldk, int tid, int nth) {
+  const int lanes = 1 << lw, lane = tid & (lanes - 1), grp = tid >> lw, ngrp = nth >> lw;
+  const float* Fb = F + base;
+  auto put = [&](int p, int k, float v) {
+    const uint16_t h = bf16_bits_rne(v);
+    Sh[p * ldk + k] = h;
+    Sl[p * ldk + k] = bf16_bits_rne(v - bf16_bits_to_float(h));
+  };
+  auto src = [&](int k, int p) {
+    const SlabRow r = tab[p];
+    float v = 0.f;
+    if (r.cl < lim && k < K) v = Fb[r.off + (int64_t)k * f_k];
+    return v;
+  };
+  if (k_fast)   // lanes along kap (contiguous in HBM)
+    gather2d<float>(lane, lanes, Kp, grp, ngrp, Pp, src, [&](int k, int p, float v) { put(p, k, v); });
+  else          // lanes along p
+    gather2d<float>(
+        lane, lanes, Pp, grp, ngrp, Kp, [&](int p, int k) { return src(k, p); },
+        [&](int p, int k, float v) { put(p, k, v); });
+}
+
+template <typename Store>
+__device__ inline void mgen_bf16x3_store(const TileGeom& tg, const uint16_t* __restrict__ Uh,
+                                         const uint16_t* __restrict__ Ul,
+                                         const uint16_t* __restrict__ Vh,
+                                         const uint16_t* __restrict__ Vl, int ldk, int kend,
+                                         const SlabRow* __restrict__ ptab,
+                                         const SlabRow* __restrict__ qtab, Store store, int lane,
+                                         int wave, int nwaves) {
+  const int npt = tg.Pp / 16, nqt = tg.Qp / 16;
+  const int lo = (lane & 15) * ldk + 8 * (lane >> 4);
+  for (int t = wave; t < npt * nqt; t += nwaves) {
+    const int pt = t / nqt, qt = t - (t / nqt) * nqt;
+    MfmaBf16::acc_t acc = Mfma<float>::zero();
+    const int ao = pt * 16 * ldk + lo, bo = qt * 16 * ldk + lo;
+    for (int k0 = 0; k0 < kend; k0 += 32) {
+      const bf16x8 a = *(const bf16x8*)(Uh + ao + k0);
+      const bf16x8 b = *(const bf16x8*)(Vh + bo + k0);
+      const bf16x8 al = *(const bf16x8*)(Ul + ao + k0);
+      const bf16x8 bl = *(const bf16x8*)(Vl + bo + k0);
+      acc = MfmaBf16::mma(a, b, acc);
+      acc = MfmaBf16::mma(a, bl, acc);
+      acc = MfmaBf16::mma(al, b, acc);
+    }
+    const int qm = qtab[qt * 16 + (lane & 15)].map;
+    if (qm >= 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pm = ptab[pt * 16 + MfmaBf16::row(lane, i)].map;
+        if (pm >= 0) store(pm + qm, acc[i]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // bf16 form of the same pass.  The tile of M_k is generated on fp32 MFMA as
 // above and rounded once (nearest even) into bf16 LDS tiles laid out
 // [row][column] (columns contiguous), as are the X_(k) rows; the Gram and
@@ -446,11 +514,12 @@ int gram_tiles_per_group() { return kGramWaves * kTPW; }
 // 16-byte load.  With X3 each value is also kept as a bf16 residual
 // (x = hi + lo) and every product is hi*hi + hi*lo + lo*hi.
 // ---------------------------------------------------------------------------
-// bf16: at most 128 VGPRs (two workgroups per CU, as for float32); the split
-// form keeps the default budget (its tiles need more than half a CU's LDS,
-// so it runs one workgroup per CU anyway)
-template <int X3, int TPW, int NW = kGramWaves>
-__global__ void __launch_bounds__(64 * NW, (X3 && NW == NW) ? 1 : 4) gram_rhs_bf16_k(MGen mg, const float* __restrict__ X,
+// bf16: NW waves of TPW tiles.  Eight waves: at most 128 VGPRs (two
+// workgroups per CU) except the split form's 16-tile instance, which keeps the
+// default budget; sixteen waves (one workgroup per CU): 128 VGPRs.  MG16: the
+// sub-network tile is generated in split bf16 (above) instead of float32.
+template <int X3, int TPW, int NW = kGramWaves, bool MG16 = false>
+__global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ? 1 : 4) gram_rhs_bf16_k(MGen mg, const float* __restrict__ X,
                                                                 XView xv, GramGeom g,
                                                                 float* __restrict__ part) {
   typedef Mfma<float> MF;
@@ -459,10 +528,17 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == NW) ? 1 : 4) gram_rhs_bf
   SlabRow* ptab = (SlabRow*)smem_raw;
   SlabRow* qtab = ptab + tg.Pp;
   SlabRow* ctab = qtab + tg.Qp;
+  // operand slabs: float32 (u_len, v_len), or with MG16 bf16 heads and
+  // tails [p][kap] with row stride g.ldk
   float* Us = (float*)(ctab + tg.tcolp);
   float* Vs = Us + tg.u_len;
+  uint16_t* const Ush = (uint16_t*)(ctab + tg.tcolp);
+  uint16_t* const Usl = Ush + (size_t)tg.Pp * g.ldk;
+  uint16_t* const Vsh = Usl + (size_t)tg.Pp * g.ldk;
+  uint16_t* const Vsl = Vsh + (size_t)tg.Qp * g.ldk;
   const int ldb = g.ldm;                         // bf16 row stride (multiple of 8)
-  uint16_t* Mh = (uint16_t*)(Vs + tg.v_len);     // [sp][ldb]
+  uint16_t* Mh = MG16 ? Vsl + (size_t)tg.Qp * g.ldk
+                      : (uint16_t*)(Vs + tg.v_len);   // [sp][ldb]
   uint16_t* Ml = Mh + (X3 ? (size_t)g.sp * ldb : 0);
   uint16_t* Xh = Ml + (size_t)g.sp * ldb;         // [xrows][ldb]
   uint16_t* Xl = Xh + (X3 ? (size_t)g.xrows * ldb : 0);
@@ -513,9 +589,14 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == NW) ? 1 : 4) gram_rhs_bf
   build_tables(mg, tg, &xv, ldb, 1, ptab, qtab, ctab, tid, (64 * NW));
   {
     // M tile(s) then X tile(s), hi and (X3) lo copies: every padding column
-    // must read as zero
+    // must read as zero; with MG16 also the bf16 slabs (the kap padding up to
+    // a multiple of 32 is never staged)
     const int nzero = (g.sp + g.xrows) * ldb * (1 + X3);
     for (int e = tid; e < nzero; e += (64 * NW)) Mh[e] = 0;
+    if (MG16) {
+      const int ns = 2 * (tg.Pp + tg.Qp) * g.ldk;
+      for (int e = tid; e < ns; e += (64 * NW)) Ush[e] = 0;
+    }
   }
   __syncthreads();
 
@@ -531,8 +612,23 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == NW) ? 1 : 4) gram_rhs_bf
 
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
-    stage_operands<float, true>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
-                                (64 * NW));
+    if constexpr (MG16) {
+      if (tu != cur_tu) {
+        const int64_t cu0 = tu * tg.TCu;
+        stage_slab_bf16(U, cu0 * mg.u_cu, mg.u_k, mg.K, tg.Kp, tg.Pp, tg.us_k == 1, tg.u_lw,
+                        ptab, mg.Cu - cu0, Ush, Usl, g.ldk, tid, 64 * NW);
+        cur_tu = tu;
+      }
+      if (tv != cur_tv) {
+        const int64_t cv0 = tv * tg.TCv;
+        stage_slab_bf16(V, cv0 * mg.v_cv, mg.v_k, mg.K, tg.Kp, tg.Qp, tg.vs_k == 1, tg.v_lw,
+                        qtab, mg.Cv - cv0, Vsh, Vsl, g.ldk, tid, 64 * NW);
+        cur_tv = tv;
+      }
+    } else {
+      stage_operands<float, true>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
+                                  (64 * NW));
+    }
     if (xrows > 0) {
       const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
       const int64_t lim_u = mg.Cu - cu0, lim_v = mg.Cv - cv0;
@@ -558,9 +654,13 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == NW) ? 1 : 4) gram_rhs_bf
       }
     }
     __syncthreads();
-    mgen_mfma_store<float>(tg, Us, Vs, ptab, qtab,
-                           [&](int idx, float v) { put(Mh, Ml, idx, v); }, lane, wave,
-                           NW);
+    if constexpr (MG16)
+      mgen_bf16x3_store(tg, Ush, Usl, Vsh, Vsl, g.ldk, tg.Kp,
+                        ptab, qtab, [&](int idx, float v) { put(Mh, Ml, idx, v); }, lane, wave,
+                        NW);
+    else
+      mgen_mfma_store<float>(tg, Us, Vs, ptab, qtab,
+                             [&](int idx, float v) { put(Mh, Ml, idx, v); }, lane, wave, NW);
     __syncthreads();
     for (int kk = 0; kk < tg.tcolp; kk += 32) {
 #pragma unroll
@@ -625,14 +725,23 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
     };
     const bool wide = g.nw == 2 * kGramWaves;   // 16 waves, 8 tiles each
     constexpr int W2 = 2 * kGramWaves, T2 = kTPW / 2;
-    if (prec == P_BF16) {
-      if (small) run(gram_rhs_bf16_k<0, 2>, kGramThreads);
-      else if (wide) run(gram_rhs_bf16_k<0, T2, W2>, 2 * kGramThreads);
-      else run(gram_rhs_bf16_k<0, kTPW>, kGramThreads);
-    } else if (prec == P_BF16X3) {
-      if (small) run(gram_rhs_bf16_k<1, 2>, kGramThreads);
-      else if (wide) run(gram_rhs_bf16_k<1, T2, W2>, 2 * kGramThreads);
-      else run(gram_rhs_bf16_k<1, kTPW>, kGramThreads);
+    if (prec == P_BF16 || prec == P_BF16X3) {
+      const bool x3 = prec == P_BF16X3, mg16 = g.mg16 != 0;
+      // instances: form x {small tiles, 16 waves, 8 waves} x generator
+      if (small) {
+        if (x3) mg16 ? run(gram_rhs_bf16_k<1, 2, kGramWaves, true>, kGramThreads)
+                     : run(gram_rhs_bf16_k<1, 2>, kGramThreads);
+        else mg16 ? run(gram_rhs_bf16_k<0, 2, kGramWaves, true>, kGramThreads)
+                  : run(gram_rhs_bf16_k<0, 2>, kGramThreads);
+      } else if (wide) {
+        if (x3) mg16 ? run(gram_rhs_bf16_k<1, T2, W2, true>, 2 * kGramThreads)
+                     : run(gram_rhs_bf16_k<1, T2, W2>, 2 * kGramThreads);
+        else mg16 ? run(gram_rhs_bf16_k<0, T2, W2, true>, 2 * kGramThreads)
+                  : run(gram_rhs_bf16_k<0, T2, W2>, 2 * kGramThreads);
+      } else {
+        if (x3) run(gram_rhs_bf16_k<1, kTPW>, kGramThreads);
+        else run(gram_rhs_bf16_k<0, kTPW>, kGramThreads);
+      }
     } else if (small) {
       run(gram_rhs_k<float, 2>, kGramThreads);
     } else if (g.tg.u_vec || g.tg.v_vec) {

@@ -65,6 +65,8 @@ struct GramGeom {
   int32_t nw;                // waves per workgroup: 8 (16 tiles each, two
                              // workgroups per CU) or 16 (8 tiles each, one
                              // workgroup per CU with all of its LDS)
+  int32_t mg16, ldk;         // bf16 forms: sub-network generated in split
+                             // bf16 from bf16 slabs of row stride ldk
 };
 
 // Launch geometry of the reconstruction Z_(k) = A_k(k) M_k.
