@@ -108,6 +108,9 @@ typedef struct {
   double f_data;       /* 1/2 ||X^{t+1} - FCTN(A^{t+1})||_F^2                 */
   double f_trace;      /* sum_k lambda_k/2 tr(A_k(k)^T L_k A_k(k))            */
   double objective;    /* f_data + f_trace                                   */
+  float ms_stage[8];   /* kernel milliseconds of the sweep per stage
+                          (FCTN_STAGE_* below), filled by fctn_sweep while
+                          per-kernel timing is on; 0 otherwise              */
 } fctn_sweep_stats;
 
 typedef struct {
@@ -123,10 +126,22 @@ size_t fctn_workspace_bytes(const fctn_desc* desc);
 /* Create a plan.  ws_dev: caller-owned device buffer of at least
  * fctn_workspace_bytes(desc) bytes, 256-byte aligned; hip_stream: the
  * hipStream_t all work is queued on (NULL = the null stream).  Builds the
- * Fourier eigenbases of every L_k (eq. 7) on the device.  Factors start at
- * zero until fctn_set_factors. */
+ * Fourier eigenbases of every L_k (eq. 7) on the device and sets the initial
+ * factors (Algorithm 1, initialization: standard normal entries): A0_host[k]
+ * is factor k in float64 with the factor layout above (host memory, copied
+ * before the call returns), or, if A0_host is NULL, the factors are drawn
+ * from `seed` with a counter-based generator: SplitMix64 words
+ * w_j = mix(seed + (j + 1) * 0x9E3779B97F4A7C15), pairs of words turned into
+ * pairs of normals by the Box-Muller transform (u1 = (w >> 11) + 1 and
+ * u2 = w >> 11 scaled by 2^-53; sqrt(-2 ln u1) cos(2 pi u2), then sin), factor
+ * 1's entries first.  Synchronizes the stream.  Errors: FCTN_E_INVALID for a
+ * bad descriptor, pointer or alignment (or a NULL A0_host[k]),
+ * FCTN_E_UNSUPPORTED for a valid problem this library does not run,
+ * FCTN_E_NOMEM if ws_bytes is too small, FCTN_E_DEVICE for a failed HIP
+ * call. */
 fctn_status fctn_plan(const fctn_desc* desc, void* ws_dev, size_t ws_bytes,
-                      void* hip_stream, fctn_plan_t* out);
+                      void* hip_stream, const double* const* A0_host, uint64_t seed,
+                      fctn_plan_t* out);
 
 /* Initial factors (Algorithm 1, initialization: standard normal entries).
  * A_host[k]: host pointer to factor k in float64 with the factor layout
@@ -164,7 +179,9 @@ fctn_status fctn_set_x(fctn_plan_t plan, const void* X_dev);
 fctn_status fctn_regrow(fctn_plan_t to, fctn_plan_t from, const double* fill_dev);
 
 /* Run `nsweeps` PAM sweeps (Algorithm 1 or 2 by desc.reuse).  If stats_host
- * is not NULL it receives the scalars of the last sweep (synchronizes). */
+ * is not NULL it receives the scalars of the last sweep and, with per-kernel
+ * timing on (fctn_profile_enable), that sweep's kernel time per stage
+ * (synchronizes). */
 fctn_status fctn_sweep(fctn_plan_t plan, int32_t nsweeps,
                        fctn_sweep_stats* stats_host);
 

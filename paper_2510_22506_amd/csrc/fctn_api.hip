@@ -903,6 +903,30 @@ fctn_status sync_checked(fctn_plan_s* P) {
   return FCTN_OK;
 }
 
+// Standard normal draws for the initial factors from a seed (Algorithm 1's
+// initialization).  Counter-based: value i of the stream depends only on
+// (seed, i).  SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) gives 64-bit
+// words w_j = mix(seed + (j + 1) * 0x9E3779B97F4A7C15); pair n of normals
+// comes from words 2n and 2n + 1 by the Box-Muller transform (u1 in (0, 1]
+// and u2 in [0, 1) from the top 53 bits): r = sqrt(-2 ln u1), values
+// r cos(2 pi u2) and r sin(2 pi u2).  Factor 1's entries take stream
+// indices 0 .. |A_1| - 1, factor 2's the next ones, and so on.
+uint64_t splitmix64(uint64_t seed, uint64_t j) {
+  uint64_t z = seed + (j + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double seeded_normal(uint64_t seed, uint64_t i) {
+  const uint64_t n = i / 2;
+  const double u1 = ((double)(splitmix64(seed, 2 * n) >> 11) + 1.0) * 0x1.0p-53;
+  const double u2 = (double)(splitmix64(seed, 2 * n + 1) >> 11) * 0x1.0p-53;
+  const double r = sqrt(-2.0 * log(u1));
+  const double a = 6.283185307179586 * u2;
+  return (i & 1) ? r * sin(a) : r * cos(a);
+}
+
 fctn_status read_slot(fctn_plan_s* P, const double* slot, fctn_sweep_stats* out) {
   double h[4];
   if (hipMemcpyAsync(h, slot, sizeof(h), hipMemcpyDeviceToHost, P->st) != hipSuccess) {
@@ -915,7 +939,21 @@ fctn_status read_slot(fctn_plan_s* P, const double* slot, fctn_sweep_stats* out)
   out->f_data = h[1];
   out->f_trace = h[2];
   out->objective = h[3];
+  for (int i = 0; i < 8; ++i) out->ms_stage[i] = 0.f;
   return FCTN_OK;
+}
+
+// ms_stage of the sweeps whose launches were recorded from record `from` on
+// (per-kernel timing on; the stream is synchronized)
+void stage_times(fctn_plan_s* P, size_t from, int nsweeps, fctn_sweep_stats* out) {
+  if (!P->prof || nsweeps <= 0) return;
+  double ms[8] = {};
+  for (size_t i = from; i < P->prof->recs.size(); ++i) {
+    float t = 0.f;
+    const ProfRec& r = P->prof->recs[i];
+    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) ms[r.stage] += t;
+  }
+  for (int i = 0; i < 8; ++i) out->ms_stage[i] = (float)(ms[i] / nsweeps);
 }
 
 // Plan set-up without host synchronization or pageable copies, so that it
@@ -1018,7 +1056,7 @@ fctn_status fctn_mode_sizes(const fctn_desc* desc, int32_t k, int64_t* s_k, int6
 }
 
 fctn_status fctn_plan(const fctn_desc* desc, void* ws_dev, size_t ws_bytes, void* hip_stream,
-                      fctn_plan_t* out) {
+                      const double* const* A0_host, uint64_t seed, fctn_plan_t* out) {
   if (!out) return FCTN_E_INVALID;
   *out = nullptr;
   fctn_plan_s* P = nullptr;
@@ -1027,6 +1065,25 @@ fctn_status fctn_plan(const fctn_desc* desc, void* ws_dev, size_t ws_bytes, void
   if (hipStreamSynchronize(P->st) != hipSuccess) {
     delete P;
     return FCTN_E_DEVICE;
+  }
+  // initial factors: the caller's, or standard normal draws from the seed
+  std::vector<std::vector<double>> drawn;
+  std::vector<const double*> ptrs(P->N);
+  if (A0_host) {
+    for (int k = 0; k < P->N; ++k) ptrs[k] = A0_host[k];
+  } else {
+    uint64_t i = 0;
+    drawn.resize(P->N);
+    for (int k = 0; k < P->N; ++k) {
+      drawn[k].resize(P->fnum[k]);
+      for (int64_t e = 0; e < P->fnum[k]; ++e) drawn[k][e] = seeded_normal(seed, i++);
+      ptrs[k] = drawn[k].data();
+    }
+  }
+  v = fctn_set_factors(P, ptrs.data());
+  if (v != FCTN_OK) {
+    delete P;
+    return v;
   }
   *out = P;
   return FCTN_OK;
@@ -1140,7 +1197,9 @@ fctn_status fctn_regrow(fctn_plan_t to, fctn_plan_t from, const double* fill_dev
 fctn_status fctn_sweep(fctn_plan_t P, int32_t nsweeps, fctn_sweep_stats* stats_host) {
   if (!P || nsweeps < 0) return FCTN_E_INVALID;
   if (P->sticky != FCTN_OK) return P->sticky;
+  size_t last_from = 0;
   for (int32_t i = 0; i < nsweeps; ++i) {
+    if (P->prof) last_from = P->prof->recs.size();
     fctn_status s = one_sweep(P);
     if (s != FCTN_OK) return s;
   }
@@ -1149,7 +1208,9 @@ fctn_status fctn_sweep(fctn_plan_t P, int32_t nsweeps, fctn_sweep_stats* stats_h
       memset(stats_host, 0, sizeof(*stats_host));
       return FCTN_OK;
     }
-    return read_slot(P, P->hist + ((P->sweeps_done - 1) % kHist) * 4, stats_host);
+    fctn_status s = read_slot(P, P->hist + ((P->sweeps_done - 1) % kHist) * 4, stats_host);
+    if (s == FCTN_OK && P->prof_on && nsweeps > 0) stage_times(P, last_from, 1, stats_host);
+    return s;
   }
   return FCTN_OK;
 }
@@ -1281,17 +1342,19 @@ fctn_status fctn_get_history(fctn_plan_t P, int32_t first, int32_t count,
     return FCTN_E_INVALID;
   std::vector<double> h((size_t)kHist * 4);
   if (hipMemcpyAsync(h.data(), P->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost,
-                     P->st) != hipSuccess ||
-      hipStreamSynchronize(P->st) != hipSuccess) {
+                     P->st) != hipSuccess) {
     P->sticky = FCTN_E_DEVICE;
     return FCTN_E_DEVICE;
   }
+  fctn_status v = sync_checked(P);
+  if (v != FCTN_OK) return v;
   for (int32_t i = 0; i < count; ++i) {
     const double* e = &h[((first + i) % kHist) * 4];
     out_host[i].rel_change = e[0];
     out_host[i].f_data = e[1];
     out_host[i].f_trace = e[2];
     out_host[i].objective = e[3];
+    for (int k = 0; k < 8; ++k) out_host[i].ms_stage[k] = 0.f;
   }
   return FCTN_OK;
 }

@@ -46,10 +46,13 @@ class fctn_desc(ctypes.Structure):
 
 class fctn_sweep_stats(ctypes.Structure):
     _fields_ = [("rel_change", ctypes.c_double), ("f_data", ctypes.c_double),
-                ("f_trace", ctypes.c_double), ("objective", ctypes.c_double)]
+                ("f_trace", ctypes.c_double), ("objective", ctypes.c_double),
+                ("ms_stage", ctypes.c_float * 8)]
 
     def as_dict(self):
-        return {n: getattr(self, n) for n, _ in self._fields_}
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "ms_stage"}
+        d["ms_stage"] = dict(zip(STAGES, [float(v) for v in self.ms_stage]))
+        return d
 
 
 class fctn_stats(ctypes.Structure):
@@ -91,7 +94,9 @@ _P = ctypes.c_void_p
 _D = ctypes.POINTER(fctn_desc)
 _SIGS = {
     "fctn_workspace_bytes": (ctypes.c_size_t, [_D]),
-    "fctn_plan": (ctypes.c_int, [_D, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "fctn_plan": (ctypes.c_int, [_D, _P, ctypes.c_size_t, _P,
+                                 ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), ctypes.c_uint64,
+                                 ctypes.POINTER(_P)]),
     "fctn_set_factors": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]),
     "fctn_set_observed": (ctypes.c_int, [_P, _P, _P]),
     "fctn_set_factors_dev": (ctypes.c_int, [_P, _P]),
@@ -203,7 +208,11 @@ class Plan:
     """One completion problem resident on the GPU (torch-owned workspace)."""
 
     def __init__(self, dims, ranks, lam=1e-2, delta=0.5, rho=0.1, precision="f32", reuse=True,
-                 order_policy=1, device="cuda:0", stream=None, extrapolation=None):
+                 order_policy=1, device="cuda:0", stream=None, extrapolation=None, A0=None,
+                 seed=0):
+        """A0: initial factors (float64 arrays with the factor shapes); None
+        draws them from `seed` in the library (fctn_plan's counter-based
+        generator).  set_factors may replace them afterwards."""
         import torch
         self.torch = torch
         self.dims = tuple(int(v) for v in dims)
@@ -219,8 +228,14 @@ class Plan:
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.elem = torch.float64 if precision == "f64" else torch.float32
         h = ctypes.c_void_p()
+        a0 = None
+        if A0 is not None:
+            arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in A0]
+            a0 = (ctypes.POINTER(ctypes.c_double) * len(arrs))(
+                *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs])
         _check(lib().fctn_plan(ctypes.byref(self.desc), _ptr(self.ws), self.ws_bytes,
-                               _stream_handle(self.stream), ctypes.byref(h)), "fctn_plan")
+                               _stream_handle(self.stream), a0, ctypes.c_uint64(int(seed)),
+                               ctypes.byref(h)), "fctn_plan")
         self.handle = h
 
     # -- inputs -------------------------------------------------------------

@@ -84,10 +84,11 @@ def test_plan_rejects_bad_arguments_without_touching_the_device(F):
     h = ctypes.c_void_p()
     lib = F.lib()
     # null workspace and misaligned workspace are rejected before any HIP call
-    assert lib.fctn_plan(ctypes.byref(d), None, 1 << 20, None, ctypes.byref(h)) == F.E_INVALID
-    assert lib.fctn_plan(ctypes.byref(d), ctypes.c_void_p(16), 1 << 20, None,
+    assert lib.fctn_plan(ctypes.byref(d), None, 1 << 20, None, None, 0,
                          ctypes.byref(h)) == F.E_INVALID
-    assert lib.fctn_plan(ctypes.byref(d), ctypes.c_void_p(4096), 16, None,
+    assert lib.fctn_plan(ctypes.byref(d), ctypes.c_void_p(16), 1 << 20, None, None, 0,
+                         ctypes.byref(h)) == F.E_INVALID
+    assert lib.fctn_plan(ctypes.byref(d), ctypes.c_void_p(4096), 16, None, None, 0,
                          ctypes.byref(h)) == F.E_NOMEM
     assert lib.fctn_sweep(None, 1, None) == F.E_INVALID
     assert lib.fctn_destroy(None) == F.E_INVALID

@@ -102,3 +102,40 @@ def test_sweep_many_equals_sweep_alone():
         s.synchronize()
     for i, p in enumerate(many):
         np.testing.assert_array_equal(p.x().cpu().numpy(), alone[i], err_msg=str(cases[i]))
+
+
+def test_plan_initial_factors_seed_and_host():
+    # fctn_plan without host factors draws them from the seed with the
+    # counter-based stream (the library's own implementation) that
+    # workloads.seeded_normal_factors restates; with host factors it takes
+    # them (as fctn_set_factors does)
+    from paper_2510_22506_amd import Plan
+    from workloads import seeded_normal_factors, init_factors
+    dims, ranks = (12, 10, 3, 5), (3, 2, 3, 2, 3, 2)
+    p = Plan(dims, ranks, precision="f64", seed=2024)
+    ref = seeded_normal_factors(2024, dims, ranks)
+    for k in range(len(dims)):
+        np.testing.assert_allclose(p.factor(k).cpu().numpy(), ref[k], rtol=1e-14, atol=1e-15)
+    A0 = init_factors(np.random.default_rng(3), dims, ranks)
+    q = Plan(dims, ranks, precision="f64", A0=A0)
+    for k in range(len(dims)):
+        np.testing.assert_array_equal(q.factor(k).cpu().numpy(), A0[k])
+
+
+def test_sweep_stats_stage_times():
+    prob = make_problem("c3", seed=13, dims=(24, 28, 3, 6), precision="f32", sr=0.2)
+    p = _plan(prob, "f32")
+    st = p.sweep(1, stats=True)
+    assert all(v == 0.0 for v in st["ms_stage"].values())
+    p.profile_enable(True)
+    st = p.sweep(2, stats=True)
+    ms = st["ms_stage"]
+    for stage in ("gram_rhs", "reduce", "solve", "transform", "reconstruct", "x_update",
+                  "stats"):
+        assert ms[stage] > 0.0, (stage, ms)
+    prof = p.profile_read(reset=True)
+    # the last sweep's stage times are at most the two sweeps' totals
+    for stage, v in ms.items():
+        assert v <= prof[stage]["ms"] * (1 + 1e-6) + 1e-6, (stage, v, prof[stage]["ms"])
+    h = p.history(0, 3)
+    assert all(all(v == 0.0 for v in e["ms_stage"].values()) for e in h)

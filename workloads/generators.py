@@ -57,6 +57,41 @@ def rank_growth_draws(seed, dims):
     return fill
 
 
+def seeded_normal_factors(seed, dims, ranks):
+    """The initial factors the library draws from a seed when a plan is made
+    without host factors: a counter-based SplitMix64 stream (Steele, Lea and
+    Flood, OOPSLA 2014; word j = mix(seed + (j + 1) * 0x9E3779B97F4A7C15)),
+    pairs of words turned into pairs of standard normals by the Box-Muller
+    transform (u1 = ((w >> 11) + 1) 2^-53 in (0, 1], u2 = (w >> 11) 2^-53;
+    sqrt(-2 ln u1) cos(2 pi u2), then sin), factor 1's entries first.  The
+    library implements the same published definition independently."""
+    M = (1 << 64) - 1
+    gamma = 0x9E3779B97F4A7C15
+
+    def words(j):
+        z = (seed + (j + 1) * gamma) & M
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    shapes = factor_shapes_of(dims, ranks)
+    total = sum(int(np.prod(sh)) for sh in shapes)
+    npairs = (total + 1) // 2
+    w = np.array([words(j) for j in range(2 * npairs)], dtype=np.uint64)
+    u1 = ((w[0::2] >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (w[1::2] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    r = np.sqrt(-2.0 * np.log(u1))
+    z = np.empty(2 * npairs)
+    z[0::2] = r * np.cos(2.0 * np.pi * u2)
+    z[1::2] = r * np.sin(2.0 * np.pi * u2)
+    out, off = [], 0
+    for sh in shapes:
+        n = int(np.prod(sh))
+        out.append(z[off:off + n].reshape(sh).copy())
+        off += n
+    return out
+
+
 def bernoulli_mask(rng, shape, sr):
     """Omega: each entry observed independently with probability sr (uint8)."""
     return (rng.random(shape) < sr).astype(np.uint8)
