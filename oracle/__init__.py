@@ -28,8 +28,9 @@ Pinning: every function is checked in ``tests/test_oracle_*.py`` against
 something other than itself (brute-force index sums, closed forms, exact
 block-decrease identities, the Eckart-Young bound, Table 1-2 counts).
 Parity unpinned: the paper's PSNR/SSIM/runtime on its real datasets (absent),
-the exact permutation drawn in the missing Figure 6 (only the Table 1 counts
-constrain it), and reuse for N >= 5 (only its X step is implemented).
+and the exact schedules drawn in the missing figures: the permutation of
+Figure 6 and the group chain for N >= 5 are readings constrained only by the
+Table 1 and Table 2 counts, which they reproduce.
 """
 
 from . import tensor, laplacian, sylvester, pam, metrics  # noqa: F401

@@ -18,8 +18,19 @@ per-sweep counts can be checked against Tables 1-2:
   A_3 x A_4 (contracted over R_34; shared by M_1 and M_2) and A_1 x A_2
   (over R_12; shared by M_3 and M_4) are cached and rebuilt only when one of
   their factors has changed; FCTN(A^{t+1}) is A_last times the sub-network of
-  the last-updated factor, which is then already current (M'_last).  For other
-  N only the X step is reused (Table 2 gives no M_k saving at N = 3).
+  the last-updated factor, which is then already current (M'_last).  For
+  N = 3 only the X step is reused (Table 2 gives no M_k saving at N = 3).
+  For N >= 5 (Table 2's N-th order case; the figures that would show the
+  schedule are missing, so the schedule is a reading of ours that reproduces
+  Table 2's Algorithm 2 counts): every M_k is a cached group of N - 2
+  factors contracted with the one remaining factor, and groups grow one
+  factor at a time from a cached smaller group.  Modes 1 and 2 share the
+  group {3..N}, grown from the pair {N-1, N} downwards; mode 3 grows the pair
+  {1, 2} by N, N-1, .., 5 (contracting with A_4); mode k >= 4 extends the
+  cached group {1, 2, k+1..N} by 3, .., k-2 (contracting with A_{k-1}).  Per
+  sweep that is 2 pairs, 3 groups of three, .., N-2 groups of N-2 factors
+  and N final contractions: Table 2's 4I^2R^{2N-3} + 6I^3R^{3N-7} + .. +
+  2N I^{N-1}R^{2N-3} (1-based modes here; the code is 0-based).
 
 Sweep order (Algorithm 2's "unordered permutation"; Figure 6 is missing from
 the source): order_policy 0 keeps (1, .., N); order_policy 1 alternates
@@ -135,9 +146,67 @@ class PairCache:
         return T, lt
 
 
-def subnetwork_M(factors, k, reuse, cache, versions, counter):
+class GroupCache:
+    """Contracted factor groups of the general-N reuse chain (N >= 5), each
+    kept with the versions of its members when it was built."""
+
+    def __init__(self):
+        self.groups = {}            # frozenset(members) -> (tensor, labels, versions)
+
+    def get(self, members, versions):
+        hit = self.groups.get(frozenset(members))
+        if hit is not None and hit[2] == tuple(versions[m] for m in sorted(members)):
+            return hit[0], hit[1]
+        return None
+
+    def put(self, members, T, lt, versions):
+        self.groups[frozenset(members)] = (T, lt, tuple(versions[m] for m in sorted(members)))
+
+
+def group_sequence(N, k):
+    """For N >= 5: the factors whose contraction, grown in this order, is the
+    group of N - 2 factors for M_k, and the remaining factor (0-based modes)."""
+    if k in (0, 1):
+        return [N - 2, N - 1] + list(range(N - 3, 1, -1)), 1 - k
+    if k == 2:
+        return [0, 1] + list(range(N - 1, 3, -1)), 3
+    return [0, 1] + list(range(N - 1, k, -1)) + list(range(2, k - 1)), k - 1
+
+
+def grown_group(factors, seq, gcache, versions, counter):
+    """The contraction of the factors in seq, reusing the longest cached
+    prefix group of seq and caching every group it builds."""
+    N = len(factors)
+    labs = [tensor.factor_labels(N, j) for j in range(N)]
+    have, T, lt = 0, None, None
+    for j in range(len(seq), 1, -1):
+        hit = gcache.get(seq[:j], versions)
+        if hit is not None:
+            have, (T, lt) = j, hit
+            break
+    if have == 0:
+        T, lt = chain(factors, seq[:2], counter, "M")
+        gcache.put(seq[:2], T, lt, versions)
+        have = 2
+    for j in range(have, len(seq)):
+        m = seq[j]
+        out = _free_labels(N, seq[:j + 1], labs)
+        T = _contract2(T, lt, factors[m], labs[m], out, counter, "M")
+        lt = out
+        gcache.put(seq[:j + 1], T, lt, versions)
+    return T, lt
+
+
+def subnetwork_M(factors, k, reuse, cache, versions, counter, gcache=None):
     """M_k (Property 1 unfolding), with or without the reuse mechanism."""
     N = len(factors)
+    if reuse and N >= 5 and gcache is not None:
+        seq, f = group_sequence(N, k)
+        G, lg = grown_group(factors, seq, gcache, versions, counter)
+        labs = [tensor.factor_labels(N, j) for j in range(N)]
+        out = _free_labels(N, seq + [f], labs)
+        T = _contract2(G, lg, factors[f], labs[f], out, counter, "M")
+        return to_property1(T, out, N, k)
     if reuse and N == 4:
         p, q = (2, 3) if k in (0, 1) else (0, 1)
         P, lp = cache.get(factors, versions, p, q, counter)
@@ -197,6 +266,7 @@ def complete(Y, mask, ranks, lam, delta, rho, sweeps, A0, tol=0.0, reuse=True,
     factors = [np.array(a, dtype=np.float64).reshape(s) for a, s in zip(A0, shapes)]
     X = np.where(mask, Y, 0.0) if X0 is None else np.array(X0, dtype=np.float64)
     cache = PairCache()
+    gcache = GroupCache()
     versions = [0] * N
     stats = {"rel_change": [], "objective": [], "blocks": [], "sweeps_done": 0}
 
@@ -205,7 +275,7 @@ def complete(Y, mask, ranks, lam, delta, rho, sweeps, A0, tol=0.0, reuse=True,
         order = sweep_order(N, t0 + t, order_policy)
         Mk = None
         for k in order:
-            Mk = subnetwork_M(factors, k, reuse, cache, versions, counter)
+            Mk = subnetwork_M(factors, k, reuse, cache, versions, counter, gcache)
             Xk = tensor.unfold(X, k)
             Ak = tensor.unfold(factors[k], k)
             G = Mk @ Mk.T

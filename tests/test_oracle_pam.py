@@ -92,6 +92,8 @@ def test_observed_bit_exact_and_nan_off_omega():
     ((9, 8, 5), (3, 2, 2), 0),
     ((5, 4, 3, 6), (2, 2, 3, 2, 2, 2), 0),
     ((5, 4, 3, 6), (2, 2, 3, 2, 2, 2), 1),
+    ((4, 3, 5, 2, 3), (2, 1, 2, 2, 3, 1, 2, 2, 1, 2), 0),
+    ((3, 2, 3, 2, 2, 3), (2, 1, 2, 1, 2, 2, 1, 2, 1, 2, 1, 2, 2, 1, 2), 0),
 ])
 def test_reuse_on_equals_off(dims, ranks, policy):
     _, Y, mask, A0 = _rand_problem(dims, ranks, seed=5)
@@ -118,9 +120,10 @@ def test_loop_subnetwork_equals_property1_unfolding(dims, ranks):
     N = len(dims)
     for reuse in (False, True):
         cache = pam.PairCache()
+        gcache = pam.GroupCache()
         versions = [0] * N
         for k in range(N):
-            M = pam.subnetwork_M(fs, k, reuse, cache, versions, None)
+            M = pam.subnetwork_M(fs, k, reuse, cache, versions, None, gcache)
             Mo = tensor.subnetwork_unfolded(fs, k)
             assert M.shape == Mo.shape
             assert np.max(np.abs(M - Mo)) <= 1e-12 * np.max(np.abs(Mo)), (reuse, k)
@@ -128,14 +131,16 @@ def test_loop_subnetwork_equals_property1_unfolding(dims, ranks):
         j = N - 1
         changed[j] = rng.standard_normal(fs[j].shape)
         k = 0
-        stale = pam.subnetwork_M(changed, k, reuse, cache, versions, None)
+        stale = pam.subnetwork_M(changed, k, reuse, cache, versions, None, gcache)
         fresh_versions = list(versions)
         fresh_versions[j] += 1
-        fresh = pam.subnetwork_M(changed, k, reuse, cache, fresh_versions, None)
+        fresh = pam.subnetwork_M(changed, k, reuse, cache, fresh_versions, None, gcache)
         Mo_new = tensor.subnetwork_unfolded(changed, k)
         assert np.max(np.abs(fresh - Mo_new)) <= 1e-12 * np.max(np.abs(Mo_new))
-        if reuse and N == 4:
-            # pair (3, 4) cached from the old factors: still the old M_1
+        if reuse and N >= 4:
+            # the group holding the last factor (pair (3, 4) for N = 4, the
+            # group {3..N} for N = 5) cached from the old factors: still the
+            # old M_1 while no version moves
             Mo_old = tensor.subnetwork_unfolded(fs, k)
             assert np.max(np.abs(stale - Mo_old)) <= 1e-12 * np.max(np.abs(Mo_old))
         else:
@@ -210,6 +215,23 @@ def test_table2_counts_algorithm1(N, I, R):
     x = 2 * sum(I**K * R**(K * (N - K) + K - 1) for K in range(2, N + 1))
     mm = 2 * N * (I**(N - 1) * R**(2 * (N - 1)) + I**N * R**(N - 1))
     assert c["M"] == m and c["X"] == x and c["gram"] + c["rhs"] == mm
+
+
+@pytest.mark.parametrize("N,I,R", [(5, 3, 2), (6, 2, 2)])
+def test_table2_counts_algorithm2(N, I, R):
+    # Table 2, Algorithm 2 column for the N-th order case: computing M_k costs
+    # 4I^2R^{2N-3} + 6I^3R^{3N-7} + .. + 2N I^{N-1}R^{2N-3} per sweep (the
+    # j-factor groups for j = 2 .. N-2, then N final contractions), every
+    # sweep; the X step reuses M'_last
+    dims, ranks = (I,) * N, (R,) * (N * (N - 1) // 2)
+    m = sum(2 * j * I**j * R**(j * (N - j) + j - 1) for j in range(2, N - 1))
+    m += 2 * N * I**(N - 1) * R**(2 * N - 3)
+    for c in _counts(dims, ranks, True, 0, 3):
+        assert c["M"] == m
+        assert c["X"] == 2 * I**N * R**(N - 1)
+    # and it is below Algorithm 1's count
+    a1 = _counts(dims, ranks, False, 0, 1)[0]["M"]
+    assert m < a1
 
 
 def test_table2_x_count_algorithm2_order3():
