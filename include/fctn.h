@@ -68,27 +68,29 @@ typedef struct fctn_plan_s* fctn_plan_t;
 
 /* Problem descriptor: the inputs of Algorithms 1-2 apart from Y and Omega. */
 typedef struct {
-  int32_t order;                    /* N; supported: N = 3 .. 6              */
+  int32_t order;                    /* N; supported: N = 3 .. 8              */
   int64_t dims[FCTN_MAX_ORDER];     /* I_1 .. I_N, each >= 1                 */
   int32_t ranks[FCTN_MAX_BONDS];    /* r_FCTN in the order above, each >= 1  */
   double lambda[FCTN_MAX_ORDER];    /* lambda_k >= 0 (eq. model_1)           */
   double delta[FCTN_MAX_ORDER];     /* delta_k > 0 (L_k, Section 3.1)        */
   double rho;                       /* proximal weight rho > 0 (eq. 3)       */
   int32_t precision;                /* fctn_precision                        */
-  int32_t reuse;                    /* 1: Algorithm 2 (Section 3.3): for
-                                       N = 4 the pair tensors A1xA2 and A3xA4
+  int32_t reuse;                    /* 1: Algorithm 2 (Sections 3.3-3.4):
+                                       for N = 4 the pair tensors A1xA2 and
+                                       A3xA4, for N >= 5 the prefix groups
+                                       A1..Aj and suffix groups Aj..AN (each
+                                       grown by one factor from its neighbour)
                                        are cached and rebuilt only when one of
                                        their factors changed.  0: Algorithm 1's
                                        work: every mode's sub-network and the
                                        FCTN(A) of the X step are contracted
                                        from the factors, rebuilding the pair
-                                       (N = 4) each time.  Both run the same
-                                       kernels on the same operands, so their
-                                       iterates are bitwise equal; only the
-                                       contraction work differs (Table 1).  For
-                                       N = 3 nothing is cached and the flag has
-                                       no effect; for N = 5, 6 the operand
-                                       groups are rebuilt every mode in both */
+                                       or the group chain each time.  Both run
+                                       the same kernels on the same operands,
+                                       so their iterates are bitwise equal;
+                                       only the contraction work differs
+                                       (Tables 1-2).  For N = 3 nothing is
+                                       cached and the flag has no effect     */
   int32_t order_policy;             /* 0: factor order 1..N every sweep;
                                        1: for N = 4 alternate (1,2,3,4) and
                                        (3,4,1,2) so a cached pair carries over
@@ -239,8 +241,8 @@ fctn_status fctn_get_factor(fctn_plan_t plan, int32_t k, double* dst_dev);
  * rho A_k(k), both float64 row-major.  The s_k index is the bond multi-index
  * of A_k in its mode order with the last bond fastest; the columns of M_k
  * and X_(k) are the other physical indices, last fastest.  For N = 4 the
- * needed pair tensor is (re)built first; for N = 5, 6 the mode's operand
- * groups (contractions of consecutive factors) are. */
+ * needed pair tensor is (re)built first; for N >= 5 the mode's operand
+ * groups (contractions of consecutive factors) are, where stale. */
 fctn_status fctn_step_gram_rhs(fctn_plan_t plan, int32_t k, double* G_dev,
                                double* B_dev);
 

@@ -101,9 +101,10 @@ def contract(X, Y, n_modes, m_modes):
 # ----------------------------------------------------------------------------
 
 def _labels(N):
-    """einsum labels: uppercase for physical modes i_k, lowercase for bonds."""
+    """einsum labels: uppercase for physical modes i_k, lowercase for bonds
+    (then the unused uppercase letters: N = 8 has 28 bonds)."""
     phys = string.ascii_uppercase[:N]
-    lower = iter(string.ascii_lowercase)
+    lower = iter(string.ascii_lowercase + string.ascii_uppercase[N:])
     bond = {}
     for (i, j) in bond_pairs(N):
         bond[(i, j)] = bond[(j, i)] = next(lower)

@@ -39,7 +39,12 @@ struct Carver {
   }
 };
 
-enum Src { SRC_F0 = 0, SRC_P12 = 10, SRC_P34 = 11, SRC_G0 = 12, SRC_G1 = 13 };
+enum Src { SRC_F0 = 0, SRC_P12 = 10, SRC_P34 = 11, SRC_GRP = 16 };
+
+// orders N >= 5: the prefix groups A_1..A_j (j = 2 .. N-2) and the suffix
+// groups A_j..A_N (j = 3 .. N-1), 1-based, each one factor more than its
+// parent group
+constexpr int kMaxGroups = 2 * (FCTN_MAX_ORDER - 3);
 
 struct ModeInfo {
   int64_t Ik, s, C, spost;
@@ -49,10 +54,18 @@ struct ModeInfo {
   GramGeom geom;
   RecGeom rg;
   int ncls;
-  // orders N >= 5: the operand groups (0: U, 1: V) that are materialized
-  bool gmat[2];
-  GroupDesc gd[2];
-  int gmem[2][kGroupMaxMembers];
+};
+
+// one cached group of the general-order chain: members[0] (x) members[1]
+// contracted over their shared bonds
+struct GroupSlot {
+  GroupDesc gd;       // member pointers are filled at launch
+  int src[2];         // SRC_F0 + factor or SRC_GRP + group
+  uint32_t fmask;     // factors contracted into the group
+  int64_t num;        // entries
+  void* buf;
+  bool built;
+  int64_t snap[FCTN_MAX_ORDER];   // factor versions it was built from
 };
 
 struct ProfRec {
@@ -107,10 +120,8 @@ struct fctn_plan_s {
   double* hist;
   double* scratch_slot;
   ModeInfo mode[FCTN_MAX_ORDER];
-  void* Gb[2];        // orders N >= 5: the current mode's operand groups
-  int64_t gnum[2];
-  int gmode;          // mode the groups were built for (-1: none)
-  int64_t gver[FCTN_MAX_ORDER];
+  GroupSlot grp[kMaxGroups];   // orders N >= 5
+  int ngrp;
   int64_t sweeps_done;
   int64_t fver[FCTN_MAX_ORDER];
   int64_t pver[2][2];
@@ -139,7 +150,7 @@ fctn_status validate(const fctn_desc* d) {
   if (d->order_policy != 0 && d->order_policy != 1) return FCTN_E_INVALID;
   if (!(d->extrap_alpha >= 0.0 && d->extrap_alpha < 1.0)) return FCTN_E_INVALID;
   if (!(d->extrap_beta >= 0.0 && d->extrap_beta <= 1.0)) return FCTN_E_INVALID;
-  if (N < 3 || N > 6) return FCTN_E_UNSUPPORTED;
+  if (N < 3) return FCTN_E_UNSUPPORTED;
   return FCTN_OK;
 }
 
@@ -154,138 +165,278 @@ void fill_ranks(const fctn_desc* d, int R[FCTN_MAX_ORDER][FCTN_MAX_ORDER]) {
   }
 }
 
-// Orders N >= 5.  The other modes split into two groups of consecutive
-// indices, S below T (at k itself when k is inside; in two halves when k is
-// the first or last mode), so that the columns (i_S, i_T) of M_k are a strided
-// view of X and the rows (bonds to k from S, then from T) follow A_k's bond
-// order.  A group of one factor is read in place; a larger group is
-// materialized as G[i_S][bonds to k][cross bonds], the cross bonds (s, t),
-// s in S, t in T, in s-major order on both sides, so that kap runs with one
-// stride through both operands.
-int64_t fstride(const fctn_plan_s* P, int f, int j) {
+// Orders N >= 5 (Algorithm 2's reuse, Section 3.4, Table 2).  For mode k the
+// other factors split into two runs of consecutive modes, U below V:
+//   k = 1, 2:        U = {A_{3-k}},       V = A_3..A_N
+//   3 <= k <= N-1:   U = A_1..A_{k-1},    V = A_{k+1}..A_N
+//   k = N:           U = A_1..A_{N-2},    V = {A_{N-1}}
+// (1-based), so that the columns (i_U, i_V) of M_k are a strided view of X
+// and the rows (bonds to k from U, then from V) follow A_k's bond order.  A
+// run of one factor is read in place; a longer run is a cached group: the
+// prefix A_1..A_j is built as (A_1..A_{j-1}) (x) A_j and the suffix A_j..A_N
+// as A_j (x) (A_{j+1}..A_N), and a group is rebuilt only when one of its
+// factors has changed since it was built.  In the fixed order 1..N a sweep
+// builds one pair and N-4 larger groups on each side.
+//
+// Layouts are lists of keys, the last fastest: a key is a physical index
+// (a == b) or a bond {a < b}.
+//   factor f:  for l = 0..N-1: l == f ? i_f : bond(f, l)          (0-based)
+//   prefix j:  i_0..i_j | bond(s, j+1), s = 0..j | bond(s, t), s = 0..j, t = j+2..N-1
+//   suffix j:  i_j..i_{N-1} | bond(t, s), s = 0..j-1, t = j..N-1
+// The prefix keeps the bonds to the next factor as one block (the rows of M
+// for mode j+1, the internal bonds of the next prefix), the suffix its bonds
+// grouped by the outside factor, so that every block M_k or a chain step
+// reads is a run of consecutive keys.
+struct Key {
+  int a, b;
+  int64_t size;
+};
+typedef std::vector<Key> Layout;
+
+Key phys_key(const fctn_plan_s* P, int l) { return Key{l, l, P->dims[l]}; }
+Key bond_key(const fctn_plan_s* P, int s, int t) {
+  return Key{std::min(s, t), std::max(s, t), P->R[s][t]};
+}
+
+Layout factor_layout(const fctn_plan_s* P, int f) {
+  Layout L;
+  for (int l = 0; l < P->N; ++l) L.push_back(l == f ? phys_key(P, f) : bond_key(P, f, l));
+  return L;
+}
+
+Layout prefix_layout(const fctn_plan_s* P, int j) {
+  Layout L;
+  for (int l = 0; l <= j; ++l) L.push_back(phys_key(P, l));
+  for (int s = 0; s <= j; ++s) L.push_back(bond_key(P, s, j + 1));
+  for (int s = 0; s <= j; ++s)
+    for (int t = j + 2; t < P->N; ++t) L.push_back(bond_key(P, s, t));
+  return L;
+}
+
+Layout suffix_layout(const fctn_plan_s* P, int j) {
+  Layout L;
+  for (int l = j; l < P->N; ++l) L.push_back(phys_key(P, l));
+  for (int s = 0; s < j; ++s)
+    for (int t = j; t < P->N; ++t) L.push_back(bond_key(P, t, s));
+  return L;
+}
+
+int find_key(const Layout& L, const Key& k) {
+  for (size_t i = 0; i < L.size(); ++i)
+    if (L[i].a == k.a && L[i].b == k.b) return (int)i;
+  return -1;
+}
+
+int64_t key_stride(const Layout& L, int i) {
   int64_t st = 1;
-  for (int l = P->N - 1; l > j; --l) st *= (l == f) ? P->dims[f] : P->R[f][l];
+  for (size_t l = i + 1; l < L.size(); ++l) st *= L[l].size;
   return st;
+}
+
+int64_t layout_numel(const Layout& L) {
+  int64_t n = 1;
+  for (const Key& k : L) n *= k.size;
+  return n;
+}
+
+// the keys sit in L consecutively and in this order: their flat index has
+// the stride of the last one
+bool block_stride(const Layout& L, const std::vector<Key>& keys, int64_t* st, int64_t* size) {
+  if (keys.empty()) return false;
+  const int i0 = find_key(L, keys[0]);
+  if (i0 < 0 || i0 + keys.size() > L.size()) return false;
+  *size = 1;
+  for (size_t q = 0; q < keys.size(); ++q) {
+    if (L[i0 + q].a != keys[q].a || L[i0 + q].b != keys[q].b) return false;
+    *size *= keys[q].size;
+  }
+  *st = key_stride(L, i0 + (int)keys.size() - 1);
+  return true;
+}
+
+// GroupDesc of out = m0 (x) m1, contracted over the keys both members hold;
+// every offset the kernel forms is checked against the member sizes
+bool chain_desc(const Layout& m0, const Layout& m1, const Layout& out, GroupDesc* gd) {
+  memset(gd, 0, sizeof(*gd));
+  gd->nm = 2;
+  const Layout* M[2] = {&m0, &m1};
+  std::vector<int64_t> dsz, dmem, dst;
+  for (size_t i = 0; i < out.size(); ++i) {
+    const int i0 = find_key(m0, out[i]), i1 = find_key(m1, out[i]);
+    if ((i0 >= 0) == (i1 >= 0)) return false;   // an output key is in exactly one member
+    const int a = i0 >= 0 ? 0 : 1;
+    const int64_t st = key_stride(*M[a], a == 0 ? i0 : i1);
+    const int64_t sz = out[i].size;
+    if (!dsz.empty() && dmem.back() == a && dst.back() == st * sz) {
+      dsz.back() *= sz;        // merge with the slower digit
+      dst.back() = st;
+    } else {
+      dsz.push_back(sz);
+      dmem.push_back(a);
+      dst.push_back(st);
+    }
+  }
+  std::vector<int64_t> isz, ist0, ist1;
+  for (size_t i = 0; i < m0.size(); ++i) {
+    if (find_key(out, m0[i]) >= 0) continue;
+    const int i1 = find_key(m1, m0[i]);
+    if (i1 < 0) return false;                      // summed in one member only
+    const int64_t s0 = key_stride(m0, (int)i), s1 = key_stride(m1, i1), sz = m0[i].size;
+    if (!isz.empty() && ist0.back() == s0 * sz && ist1.back() == s1 * sz) {
+      isz.back() *= sz;
+      ist0.back() = s0;
+      ist1.back() = s1;
+    } else {
+      isz.push_back(sz);
+      ist0.push_back(s0);
+      ist1.push_back(s1);
+    }
+  }
+  for (const Key& k : m1)
+    if (find_key(out, k) < 0 && find_key(m0, k) < 0) return false;
+  if (dsz.size() > (size_t)kGroupMaxDigits || isz.size() > (size_t)kGroupMaxDigits) return false;
+  int64_t mx[2] = {0, 0}, inner = 1;
+  for (size_t d = 0; d < dsz.size(); ++d) {
+    gd->dsize[d] = (int32_t)dsz[d];
+    gd->dmem[d] = (int32_t)dmem[d];
+    gd->dstr[d] = (int32_t)dst[d];
+    mx[dmem[d]] += (dsz[d] - 1) * dst[d];
+  }
+  for (size_t i = 0; i < isz.size(); ++i) {
+    gd->isize[i] = (int32_t)isz[i];
+    gd->imem0[i] = 0;
+    gd->istr0[i] = (int32_t)ist0[i];
+    gd->imem1[i] = 1;
+    gd->istr1[i] = (int32_t)ist1[i];
+    mx[0] += (isz[i] - 1) * ist0[i];
+    mx[1] += (isz[i] - 1) * ist1[i];
+    inner *= isz[i];
+  }
+  gd->nd = (int32_t)dsz.size();
+  gd->ni = (int32_t)isz.size();
+  const int64_t total = layout_numel(out);
+  if (total >= ((int64_t)1 << 31) || inner > kGroupMaxInner) return false;
+  for (int a = 0; a < 2; ++a)
+    if (mx[a] >= layout_numel(*M[a]) || layout_numel(*M[a]) >= ((int64_t)1 << 31)) return false;
+  gd->total = (int32_t)total;
+  gd->inner = (int32_t)inner;
+  return true;
+}
+
+int prefix_gid(int j) { return j - 1; }                  // j = 1 .. N-3 (0-based)
+int suffix_gid(int N, int j) { return (N - 3) + (j - 2); }  // j = 2 .. N-2
+
+// the operand of consecutive modes lo..hi: a factor, a prefix or a suffix
+bool run_operand(const fctn_plan_s* P, int lo, int hi, int* src, Layout* L) {
+  const int N = P->N;
+  if (lo == hi) {
+    *src = SRC_F0 + lo;
+    *L = factor_layout(P, lo);
+  } else if (lo == 0 && hi >= 1 && hi <= N - 3) {
+    *src = SRC_GRP + prefix_gid(hi);
+    *L = prefix_layout(P, hi);
+  } else if (hi == N - 1 && lo >= 2 && lo <= N - 2) {
+    *src = SRC_GRP + suffix_gid(N, lo);
+    *L = suffix_layout(P, lo);
+  } else {
+    return false;
+  }
+  return true;
+}
+
+bool setup_groups(fctn_plan_s* P) {
+  const int N = P->N;
+  P->ngrp = 2 * (N - 3);
+  for (int j = 1; j <= N - 3; ++j) {             // prefixes, each from the previous
+    GroupSlot& G = P->grp[prefix_gid(j)];
+    Layout m0 = j == 1 ? factor_layout(P, 0) : prefix_layout(P, j - 1);
+    G.src[0] = j == 1 ? SRC_F0 + 0 : SRC_GRP + prefix_gid(j - 1);
+    G.src[1] = SRC_F0 + j;
+    G.fmask = (2u << j) - 1;
+    const Layout out = prefix_layout(P, j);
+    if (!chain_desc(m0, factor_layout(P, j), out, &G.gd)) return false;
+    G.num = layout_numel(out);
+  }
+  for (int j = N - 2; j >= 2; --j) {              // suffixes, each from the next
+    GroupSlot& G = P->grp[suffix_gid(N, j)];
+    Layout m1 = j == N - 2 ? factor_layout(P, N - 1) : suffix_layout(P, j + 1);
+    G.src[0] = SRC_F0 + j;
+    G.src[1] = j == N - 2 ? SRC_F0 + N - 1 : SRC_GRP + suffix_gid(N, j + 1);
+    G.fmask = ((1u << N) - 1) & ~((1u << j) - 1);
+    const Layout out = suffix_layout(P, j);
+    if (!chain_desc(factor_layout(P, j), m1, out, &G.gd)) return false;
+    G.num = layout_numel(out);
+  }
+  return true;
+}
+
+// MGen strides of one operand: rows (its bonds to k), columns (its physical
+// indices) and kap (the bonds to the other operand, in `kap` order) must each
+// be a run of consecutive keys of its layout, and nothing else may be in it
+bool operand_strides(const Layout& L, const std::vector<Key>& rows, const std::vector<Key>& cols,
+                     const std::vector<Key>& kap, int64_t* r_st, int64_t* c_st, int64_t* k_st,
+                     int64_t* R, int64_t* C, int64_t* K) {
+  if (L.size() != rows.size() + cols.size() + kap.size()) return false;
+  return block_stride(L, rows, r_st, R) && block_stride(L, cols, c_st, C) &&
+         block_stride(L, kap, k_st, K);
 }
 
 bool setup_mode_general(fctn_plan_s* P, int k) {
   const int N = P->N;
   const int64_t* I = P->dims;
-  int(*R)[FCTN_MAX_ORDER] = P->R;
   ModeInfo& m = P->mode[k];
   MGen& g = m.mg;
   XView& x = m.xv;
-  int S[FCTN_MAX_ORDER], T[FCTN_MAX_ORDER], ns = 0, nt = 0;
-  int split;
-  if (k > 0 && k < N - 1) split = k;            // S = 0..k-1, T = k+1..N-1
-  else if (k == 0) split = 1 + (N - 1) / 2;     // S = 1..split-1
-  else split = (N - 1 + 1) / 2;                 // S = 0..split-1, T = split..N-2
-  for (int j = 0; j < N; ++j) {
-    if (j == k) continue;
-    if (j < split) S[ns++] = j; else T[nt++] = j;
+  int ulo, uhi, vlo, vhi;
+  if (k <= 1) {
+    ulo = uhi = 1 - k;
+    vlo = 2;
+    vhi = N - 1;
+  } else if (k <= N - 2) {
+    ulo = 0;
+    uhi = k - 1;
+    vlo = k + 1;
+    vhi = N - 1;
+  } else {
+    ulo = 0;
+    uhi = N - 3;
+    vlo = vhi = N - 2;
   }
-  if (ns < 1 || nt < 1 || ns > kGroupMaxMembers || nt > kGroupMaxMembers) return false;
-  int64_t Kc = 1;
-  for (int a = 0; a < ns; ++a)
-    for (int b = 0; b < nt; ++b) Kc *= R[S[a]][T[b]];
-  g.K = (int32_t)Kc;
-  for (int role = 0; role < 2; ++role) {
-    const int* X = role == 0 ? S : T;
-    const int nx = role == 0 ? ns : nt;
-    int64_t Rk = 1, Cx = 1;
-    for (int a = 0; a < nx; ++a) {
-      Rk *= R[X[a]][k];
-      Cx *= I[X[a]];
-    }
-    int64_t r_st, c_st, k_st;
-    m.gmat[role] = nx > 1;
-    if (nx == 1) {
-      const int f = X[0];
-      const int* Y = role == 0 ? T : S;
-      const int ny = role == 0 ? nt : ns;
-      r_st = fstride(P, f, k);
-      c_st = fstride(P, f, f);
-      k_st = fstride(P, f, Y[ny - 1]);
-    } else {
-      r_st = Kc;
-      c_st = Rk * Kc;
-      k_st = 1;
-      GroupDesc& gd = m.gd[role];
-      memset(&gd, 0, sizeof(gd));
-      gd.nm = nx;
-      for (int a = 0; a < nx; ++a) m.gmem[role][a] = X[a];
-      int nd = 0;
-      auto digit = [&](int64_t size) -> int {
-        if (nd >= kGroupMaxDigits) return -1;
-        gd.dsize[nd] = size;
-        return nd++;
-      };
-      int64_t mx[kGroupMaxMembers] = {0, 0, 0, 0, 0, 0};   // largest offset per member
-      auto put = [&](int d, int a, int64_t st) {
-        gd.dmem[d] = a;
-        gd.dstr[d] = (int32_t)st;
-        mx[a] += (gd.dsize[d] - 1) * st;
-      };
-      for (int a = 0; a < nx; ++a) {          // physical indices
-        const int d = digit(I[X[a]]);
-        if (d < 0) return false;
-        put(d, a, fstride(P, X[a], X[a]));
-      }
-      for (int a = 0; a < nx; ++a) {          // bonds to k
-        const int d = digit(R[X[a]][k]);
-        if (d < 0) return false;
-        put(d, a, fstride(P, X[a], k));
-      }
-      for (int a = 0; a < ns; ++a)            // cross bonds, s-major
-        for (int b = 0; b < nt; ++b) {
-          const int d = digit(R[S[a]][T[b]]);
-          if (d < 0) return false;
-          if (role == 0) put(d, a, fstride(P, S[a], T[b]));
-          else put(d, b, fstride(P, T[b], S[a]));
-        }
-      gd.nd = nd;
-      int ni = 0;
-      int64_t inner = 1;
-      for (int a = 0; a < nx; ++a)            // bonds inside the group
-        for (int b = a + 1; b < nx; ++b) {
-          if (ni >= kGroupMaxDigits) return false;
-          const int64_t sz = R[X[a]][X[b]];
-          gd.isize[ni] = (int32_t)sz;
-          gd.imem0[ni] = a;
-          gd.istr0[ni] = (int32_t)fstride(P, X[a], X[b]);
-          gd.imem1[ni] = b;
-          gd.istr1[ni] = (int32_t)fstride(P, X[b], X[a]);
-          mx[a] += (sz - 1) * gd.istr0[ni];
-          mx[b] += (sz - 1) * gd.istr1[ni];
-          inner *= sz;
-          ++ni;
-        }
-      gd.ni = ni;
-      const int64_t total = Cx * Rk * Kc;
-      // entry count and every offset the kernel forms fit 31 bits and stay
-      // inside the member factors
-      if (total >= ((int64_t)1 << 31) || inner > kGroupMaxInner) return false;
-      for (int a = 0; a < nx; ++a)
-        if (mx[a] >= P->fnum[X[a]]) return false;
-      gd.total = (int32_t)total;
-      gd.inner = (int32_t)inner;
-      P->gnum[role] = std::max(P->gnum[role], total);
-    }
-    int64_t xs = 1;
-    for (int l = X[nx - 1] + 1; l < N; ++l) xs *= I[l];
-    if (role == 0) {
-      m.u_src = nx == 1 ? SRC_F0 + X[0] : SRC_G0;
-      g.u_ru = r_st; g.u_cu = c_st; g.u_k = k_st; g.Ru = (int32_t)Rk; g.Cu = Cx;
-      x.x_cu = xs;
-    } else {
-      m.v_src = nx == 1 ? SRC_F0 + X[0] : SRC_G1;
-      g.v_rv = r_st; g.v_cv = c_st; g.v_k = k_st; g.Rv = (int32_t)Rk; g.Cv = Cx;
-      x.x_cv = xs;
-    }
+  Layout LU, LV;
+  if (!run_operand(P, ulo, uhi, &m.u_src, &LU) || !run_operand(P, vlo, vhi, &m.v_src, &LV))
+    return false;
+  std::vector<Key> ru, cu, rv, cv, kap;
+  for (int u = ulo; u <= uhi; ++u) {
+    ru.push_back(bond_key(P, u, k));
+    cu.push_back(phys_key(P, u));
   }
-  int64_t xk = 1;
-  for (int l = k + 1; l < N; ++l) xk *= I[l];
-  x.x_ik = xk;
+  for (int v = vlo; v <= vhi; ++v) {
+    rv.push_back(bond_key(P, v, k));
+    cv.push_back(phys_key(P, v));
+  }
+  for (const Key& key : LU)
+    if (key.a != key.b) {
+      const int o = key.a >= ulo && key.a <= uhi ? key.b : key.a;
+      if (o >= vlo && o <= vhi) kap.push_back(key);
+    }
+  int64_t Ru, Cu, Ku, Rv, Cv, Kv;
+  if (!operand_strides(LU, ru, cu, kap, &g.u_ru, &g.u_cu, &g.u_k, &Ru, &Cu, &Ku) ||
+      !operand_strides(LV, rv, cv, kap, &g.v_rv, &g.v_cv, &g.v_k, &Rv, &Cv, &Kv))
+    return false;
+  if (Ku != Kv || Ru * Rv != m.s || Ku >= ((int64_t)1 << 31)) return false;
+  g.Ru = (int32_t)Ru;
+  g.Rv = (int32_t)Rv;
+  g.K = (int32_t)Ku;
+  g.Cu = Cu;
+  g.Cv = Cv;
+  auto xstride = [&](int l) {
+    int64_t st = 1;
+    for (int q = l + 1; q < N; ++q) st *= I[q];
+    return st;
+  };
+  x.x_cu = xstride(uhi);
+  x.x_cv = xstride(vhi);
+  x.x_ik = xstride(k);
   return true;
 }
 
@@ -296,6 +447,7 @@ bool setup_modes(fctn_plan_s* P) {
   const int N = P->N;
   const int64_t* I = P->dims;
   int(*R)[FCTN_MAX_ORDER] = P->R;
+  if (N >= 5 && !setup_groups(P)) return false;
   for (int k = 0; k < N; ++k) {
     ModeInfo& m = P->mode[k];
     m.Ik = I[k];
@@ -626,7 +778,7 @@ size_t carve(fctn_plan_s* P, char* base) {
     part_bytes = std::max(part_bytes, (size_t)m.geom.nSplit * m.geom.nTiles * 256 * acc_es);
   }
   for (int p = 0; p < 2; ++p) P->P[p] = (N == 4) ? c.take(P->pnum[p] * es) : nullptr;
-  for (int r = 0; r < 2; ++r) P->Gb[r] = P->gnum[r] > 0 ? c.take(P->gnum[r] * es) : nullptr;
+  for (int q = 0; q < P->ngrp; ++q) P->grp[q].buf = c.take(P->grp[q].num * es);
   P->part = c.take(part_bytes);
   P->part_cur = P->part;
   P->part_bytes = part_bytes;
@@ -645,7 +797,6 @@ size_t carve(fctn_plan_s* P, char* base) {
 
 bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
   memset(P, 0, sizeof(*P));
-  P->gmode = -1;
   P->d = *d;
   P->N = d->order;
   P->prec = d->precision;
@@ -691,8 +842,7 @@ bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
 const void* src_ptr(fctn_plan_s* P, int src) {
   if (src == SRC_P12) return P->P[0];
   if (src == SRC_P34) return P->P[1];
-  if (src == SRC_G0) return P->Gb[0];
-  if (src == SRC_G1) return P->Gb[1];
+  if (src >= SRC_GRP) return P->grp[src - SRC_GRP].buf;
   return P->Aw[src - SRC_F0];
 }
 
@@ -755,23 +905,37 @@ int pair_of_mode(int N, int k) {
   return (k <= 1) ? 1 : 0;
 }
 
-// orders N >= 5: (re)build mode k's materialized operand groups unless they
-// were built for mode k from the same factors
-fctn_status ensure_groups(fctn_plan_s* P, int k) {
-  bool fresh = P->gmode == k;
+// orders N >= 5: (re)build group q (and first, where needed, the group it
+// grows from) unless it was built from the current versions of its factors;
+// with force (Algorithm 1) every call rebuilds the chain from the factors
+fctn_status ensure_group(fctn_plan_s* P, int q, bool force) {
+  GroupSlot& G = P->grp[q];
+  bool fresh = G.built && !force;
   for (int f = 0; f < P->N && fresh; ++f)
-    if (f != k && P->gver[f] != P->fver[f]) fresh = false;
+    if (((G.fmask >> f) & 1u) && G.snap[f] != P->fver[f]) fresh = false;
   if (fresh) return FCTN_OK;
-  const ModeInfo& m = P->mode[k];
-  for (int r = 0; r < 2; ++r) {
-    if (!m.gmat[r]) continue;
-    GroupDesc gd = m.gd[r];
-    for (int a = 0; a < gd.nm; ++a) gd.F[a] = P->Aw[m.gmem[r][a]];
-    FCTN_TIMED(P, FCTN_STAGE_PAIR, 2.0 * gd.total * gd.inner * (gd.nm - 1),
-               (double)gd.total * P->es, launch_group(P->prec, gd, P->Gb[r], P->st));
+  GroupDesc gd = G.gd;
+  for (int a = 0; a < 2; ++a) {
+    if (G.src[a] >= SRC_GRP) {
+      fctn_status s = ensure_group(P, G.src[a] - SRC_GRP, force);
+      if (s != FCTN_OK) return s;
+    }
+    gd.F[a] = src_ptr(P, G.src[a]);
   }
-  P->gmode = k;
-  for (int f = 0; f < P->N; ++f) P->gver[f] = P->fver[f];
+  FCTN_TIMED(P, FCTN_STAGE_PAIR, 2.0 * gd.total * gd.inner,
+             (double)gd.total * P->es, launch_group(P->prec, gd, G.buf, P->st));
+  G.built = true;
+  for (int f = 0; f < P->N; ++f) G.snap[f] = P->fver[f];
+  return FCTN_OK;
+}
+
+fctn_status ensure_groups(fctn_plan_s* P, int k) {
+  const ModeInfo& m = P->mode[k];
+  for (int src : {m.u_src, m.v_src})
+    if (src >= SRC_GRP) {
+      fctn_status s = ensure_group(P, src - SRC_GRP, P->d.reuse == 0);
+      if (s != FCTN_OK) return s;
+    }
   return FCTN_OK;
 }
 

@@ -53,9 +53,16 @@ def test_workspace_bytes_and_validation(F):
         assert F.fctn_workspace_bytes(b) == 0
     assert F.fctn_workspace_bytes(F.make_desc((32, 32, 8), (3, 3, 3), precision="f64",
                                               extrapolation=(0.5, 0.5))) == n
-    # valid for the method, outside the library's support: N = 7, N = 2, rank
-    # products above 192
-    assert F.fctn_workspace_bytes(F.make_desc((3,) * 7, (2,) * 21)) == 0
+    # orders up to 8 plan when their rank products fit the solve
+    assert F.fctn_workspace_bytes(F.make_desc((3,) * 7, (2,) * 21)) > 0
+    r8 = (1, 2, 1, 2, 2, 1, 1, 2, 1, 2, 1, 1, 2, 2, 1, 2, 1, 1, 2, 1, 2, 2, 1, 1, 2, 1, 2, 1)
+    assert F.fctn_workspace_bytes(F.make_desc((2, 3, 2, 2, 3, 2, 2, 3), r8)) > 0
+    # valid for the method, outside the library's support: N = 2, rank
+    # products above 192 (3^6 at every mode of this order 7 tensor), and an
+    # order 8 tensor whose middle modes have 2^16 cross bonds between the two
+    # operand runs (a slab of them does not fit in LDS)
+    assert F.fctn_workspace_bytes(F.make_desc((3,) * 7, (3,) * 21)) == 0
+    assert F.fctn_workspace_bytes(F.make_desc((3,) * 8, (2,) * 28)) == 0
     assert F.fctn_workspace_bytes(F.make_desc((5, 4), (2,))) == 0
     assert F.fctn_workspace_bytes(F.make_desc((8, 8, 8), (16, 16, 2))) == 0
 

@@ -1,9 +1,13 @@
-"""GPU parity at orders 5 and 6 (Table 2's N-th order case): whole PAM sweeps
+"""GPU parity at orders 5 to 8 (Table 2's N-th order case): whole PAM sweeps
 through the C ABI against the FP64 oracle on the same seeded inputs.  Each
-mode's sub-network is generated from two operand groups of consecutive
-factors (a group of one factor read in place, larger groups contracted into
-a small tensor per mode).  float64 to 1e-9, float32 to 1e-5, split bf16 to
-2e-4; observed entries bit for bit; per-sweep objective and relative change."""
+mode's sub-network is generated from two operand runs of consecutive factors:
+a run of one factor is read in place, a longer one is a cached prefix or
+suffix group, grown one factor at a time from its neighbour group and rebuilt
+only when one of its factors changed (Algorithm 2's reuse, Section 3.4).
+float64 to 1e-9, float32 to 1e-5, split bf16 to 2e-4; observed entries bit
+for bit; per-sweep objective and relative change.  With reuse each group is
+contracted once per sweep; Algorithm 1 (reuse off) rebuilds the chains for
+every mode and gives the same iterates bit for bit."""
 
 import numpy as np
 import pytest
@@ -17,6 +21,9 @@ CASES = [
     ((9, 7, 3, 4, 5), (2, 3, 1, 2, 3, 1, 2, 2, 1, 3)),
     ((6, 5, 4, 3, 7), (3, 2, 2, 3, 2, 1, 2, 3, 2, 2)),
     ((4, 3, 5, 2, 3, 4), (2, 1, 2, 2, 1, 2, 1, 2, 3, 1, 2, 2, 2, 1, 2)),
+    ((3, 4, 2, 3, 2, 3, 4), (2, 1, 2, 2, 1, 1, 2, 1, 2, 2, 1, 2, 1, 2, 2, 1, 1, 2, 2, 1, 2)),
+    ((2, 3, 2, 2, 3, 2, 2, 3), (1, 2, 1, 2, 2, 1, 1, 2, 1, 2, 1, 1, 2, 2, 1, 2, 1, 1, 2, 1, 2,
+                                2, 1, 1, 2, 1, 2, 1)),
 ]
 TOL = {"f64": 1e-9, "f32": 1e-5, "bf16x3": 2e-4}
 
@@ -79,3 +86,30 @@ def test_order5_extrapolation_and_rank_growth():
                                              extrapolation=(0.5, 0.5))
     assert [h["ranks"] for h in hist] == so["ranks"]
     assert _rel(Xg, Xo) <= 1e-9
+
+
+@pytest.mark.parametrize("dims,ranks", CASES[:2] + CASES[3:4])
+def test_group_chain_builds(dims, ranks):
+    # with reuse every one of the 2(N-3) prefix/suffix groups is contracted
+    # exactly once per sweep in the order 1..N; without reuse the chains are
+    # contracted again for every mode (and the X step), with the same iterates
+    from paper_2510_22506_amd import Plan
+    N = len(dims)
+    rng = np.random.default_rng(35)
+    mask = (rng.random(dims) < 0.3).astype(np.uint8)
+    Y = np.where(mask != 0, rng.random(dims), 0.0)
+    A0 = init_factors(rng, dims, ranks)
+    xs, launches = [], []
+    for reuse in (True, False):
+        p = Plan(dims, ranks, 1e-2, 0.5, 0.1, precision="f64", reuse=reuse)
+        p.set_factors(A0)
+        p.set_observed(Y, mask)
+        p.sweep(1)
+        p.profile_enable(True)
+        p.sweep(3)
+        launches.append(p.profile_read(reset=True)["pair"]["launches"])
+        xs.append(p.x().cpu().numpy())
+        p.close()
+    assert launches[0] == 3 * 2 * (N - 3), launches
+    assert launches[1] > launches[0], launches
+    np.testing.assert_array_equal(xs[0], xs[1])

@@ -21,6 +21,10 @@ def _factors(dims, ranks, seed=0):
     ((3, 2, 4, 2), (1, 2, 3, 2, 1, 2)),
     ((2, 3, 2, 2, 2), (2, 1, 2, 2, 1, 2, 1, 2, 2, 1)),
     ((2, 2, 1, 2, 2, 2), (2, 1, 1, 2, 1, 1, 2, 1, 2, 2, 1, 1, 2, 1, 2)),
+    # orders 7 and 8 (8 has more bonds than lowercase einsum labels)
+    ((2, 1, 2, 2, 1, 2, 2), (2, 1, 1, 1, 1, 2, 1, 1, 2, 1, 1, 1, 1, 2, 1, 1, 1, 1, 1, 2, 1)),
+    ((2, 2, 1, 2, 1, 2, 1, 2), (2, 1, 1, 1, 1, 1, 2, 1, 1, 2, 1, 1, 1, 1, 1, 1, 1, 2, 1,
+                                1, 1, 1, 1, 1, 2, 1, 1, 2)),
 ])
 def test_fctn_matches_bruteforce(dims, ranks):
     fs = _factors(dims, ranks)
