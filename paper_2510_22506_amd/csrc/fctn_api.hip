@@ -102,7 +102,7 @@ struct fctn_plan_s {
   int64_t fnum[FCTN_MAX_ORDER];
   void* P[2];
   int64_t pnum[2];
-  PairDesc pd[2];
+  GroupDesc pgd[2];
   void* part;
   void* part_cur;    // where this call's split-K partials go: part, or the
                      // static scratch array (fctn_sweep_noalloc)
@@ -254,11 +254,52 @@ bool block_stride(const Layout& L, const std::vector<Key>& keys, int64_t* st, in
   return true;
 }
 
+// launch shape of the contraction kernel: the inner block is the smallest
+// run of trailing output digits with at least 256 entries (four a lane)
+// whose member rows fit the LDS budget; short blocks share a pass of at
+// least 256 entries
+bool group_launch_shape(GroupDesc* gd, size_t es) {
+  const int64_t ip = (gd->inner + 3) / 4 * 4;
+  auto lds = [&](int64_t sin, int64_t s0, int64_t s1, int64_t no) {
+    return (int64_t)es * no * (s0 + s1) * ip + 4 * (sin + s0 + s1 + 2 * ip + 2 * no);
+  };
+  int ds = gd->nd;
+  int64_t sin = 1, s0 = 1, s1 = 1, bs = 1, b0 = 1, b1 = 1;
+  for (int d = gd->nd - 1; d >= 0; --d) {
+    sin *= gd->dsize[d];
+    (gd->dmem[d] == 0 ? s0 : s1) *= gd->dsize[d];
+    if (sin > 4096 || lds(sin, s0, s1, 1) > kGroupMaxLds) break;
+    ds = d;
+    bs = sin;
+    b0 = s0;
+    b1 = s1;
+    if (sin >= 256) break;
+  }
+  int64_t no = std::max<int64_t>(1, (256 + bs - 1) / bs);
+  while (no > 1 && lds(bs, b0, b1, no) > kGroupMaxLds) --no;
+  if (lds(bs, b0, b1, no) > kGroupMaxLds) return false;
+  gd->ds = ds;
+  gd->sin = (int32_t)bs;
+  gd->sin0 = (int32_t)b0;
+  gd->sin1 = (int32_t)b1;
+  gd->innerp = (int32_t)ip;
+  gd->no = (int32_t)no;
+  gd->nouter = (int32_t)(gd->total / bs);
+  gd->lds_bytes = (int32_t)lds(bs, b0, b1, no);
+  for (int d = ds; d < gd->nd; ++d) gd->m_dsize[d] = div_magic((uint32_t)gd->dsize[d]);
+  gd->m_ip = div_magic((uint32_t)ip);
+  gd->m_n0 = div_magic((uint32_t)b0);
+  gd->m_n1 = div_magic((uint32_t)b1);
+  gd->m_nin = div_magic((uint32_t)bs);
+  // the quotients formed with these multipliers stay below 2^16
+  return no * (b0 + b1) * ip < 65536 && no * bs < 65536;
+}
+
 // GroupDesc of out = m0 (x) m1, contracted over the keys both members hold;
 // every offset the kernel forms is checked against the member sizes
-bool chain_desc(const Layout& m0, const Layout& m1, const Layout& out, GroupDesc* gd) {
+bool chain_desc(const Layout& m0, const Layout& m1, const Layout& out, size_t es,
+                GroupDesc* gd) {
   memset(gd, 0, sizeof(*gd));
-  gd->nm = 2;
   const Layout* M[2] = {&m0, &m1};
   std::vector<int64_t> dsz, dmem, dst;
   for (size_t i = 0; i < out.size(); ++i) {
@@ -304,9 +345,7 @@ bool chain_desc(const Layout& m0, const Layout& m1, const Layout& out, GroupDesc
   }
   for (size_t i = 0; i < isz.size(); ++i) {
     gd->isize[i] = (int32_t)isz[i];
-    gd->imem0[i] = 0;
     gd->istr0[i] = (int32_t)ist0[i];
-    gd->imem1[i] = 1;
     gd->istr1[i] = (int32_t)ist1[i];
     mx[0] += (isz[i] - 1) * ist0[i];
     mx[1] += (isz[i] - 1) * ist1[i];
@@ -320,7 +359,7 @@ bool chain_desc(const Layout& m0, const Layout& m1, const Layout& out, GroupDesc
     if (mx[a] >= layout_numel(*M[a]) || layout_numel(*M[a]) >= ((int64_t)1 << 31)) return false;
   gd->total = (int32_t)total;
   gd->inner = (int32_t)inner;
-  return true;
+  return group_launch_shape(gd, es);
 }
 
 int prefix_gid(int j) { return j - 1; }                  // j = 1 .. N-3 (0-based)
@@ -354,7 +393,7 @@ bool setup_groups(fctn_plan_s* P) {
     G.src[1] = SRC_F0 + j;
     G.fmask = (2u << j) - 1;
     const Layout out = prefix_layout(P, j);
-    if (!chain_desc(m0, factor_layout(P, j), out, &G.gd)) return false;
+    if (!chain_desc(m0, factor_layout(P, j), out, P->es, &G.gd)) return false;
     G.num = layout_numel(out);
   }
   for (int j = N - 2; j >= 2; --j) {              // suffixes, each from the next
@@ -364,7 +403,7 @@ bool setup_groups(fctn_plan_s* P) {
     G.src[1] = j == N - 2 ? SRC_F0 + N - 1 : SRC_GRP + suffix_gid(N, j + 1);
     G.fmask = ((1u << N) - 1) & ~((1u << j) - 1);
     const Layout out = suffix_layout(P, j);
-    if (!chain_desc(factor_layout(P, j), m1, out, &G.gd)) return false;
+    if (!chain_desc(factor_layout(P, j), m1, out, P->es, &G.gd)) return false;
     G.num = layout_numel(out);
   }
   return true;
@@ -512,16 +551,14 @@ bool setup_modes(fctn_plan_s* P) {
     const int64_t I1 = I[0], I2 = I[1], I3 = I[2], I4 = I[3];
     const int64_t R12 = R[0][1], R13 = R[0][2], R14 = R[0][3];
     const int64_t R23 = R[1][2], R24 = R[1][3], R34 = R[2][3];
-    PairDesc& a = P->pd[0];   // P12[(i1,i2)][(r13,r23)][(r14,r24)], contracted over r12
-    a.a_i = R12 * R13 * R14; a.a_1 = R14; a.a_2 = 1; a.a_k = R13 * R14;
-    a.b_i = R23 * R24; a.b_1 = R24; a.b_2 = 1; a.b_k = I2 * R23 * R24;
-    a.Ia = (int)I1; a.Ib = (int)I2; a.n1a = (int)R13; a.n2a = (int)R14; a.n1b = (int)R23;
-    a.n2b = (int)R24; a.K = (int)R12;
-    PairDesc& b = P->pd[1];   // P34[(i3,i4)][(r13,r14)][(r23,r24)], contracted over r34
-    b.a_i = R34; b.a_1 = R23 * I3 * R34; b.a_2 = I3 * R34; b.a_k = 1;
-    b.b_i = 1; b.b_1 = R24 * R34 * I4; b.b_2 = R34 * I4; b.b_k = I4;
-    b.Ia = (int)I3; b.Ib = (int)I4; b.n1a = (int)R13; b.n2a = (int)R23; b.n1b = (int)R14;
-    b.n2b = (int)R24; b.K = (int)R34;
+    // P12[(i1,i2)][(r13,r23)][(r14,r24)], contracted over r12, and
+    // P34[(i3,i4)][(r13,r14)][(r23,r24)], contracted over r34: the prefix
+    // and suffix groups of the general-order chain at N = 4
+    if (!chain_desc(factor_layout(P, 0), factor_layout(P, 1), prefix_layout(P, 1), P->es,
+                    &P->pgd[0]) ||
+        !chain_desc(factor_layout(P, 2), factor_layout(P, 3), suffix_layout(P, 2), P->es,
+                    &P->pgd[1]))
+      return false;
     P->pnum[0] = I1 * I2 * R13 * R14 * R23 * R24;
     P->pnum[1] = I3 * I4 * R13 * R14 * R23 * R24;
   }
@@ -888,12 +925,12 @@ fctn_status ensure_pair(fctn_plan_s* P, int p, bool force) {
   const int fa = p == 0 ? 0 : 2, fb = fa + 1;
   if (!force && P->pvalid[p] && P->pver[p][0] == P->fver[fa] && P->pver[p][1] == P->fver[fb])
     return FCTN_OK;
-  PairDesc pd = P->pd[p];
-  pd.Fa = P->Aw[fa];
-  pd.Fb = P->Aw[fb];
-  FCTN_TIMED(P, FCTN_STAGE_PAIR, 2.0 * P->pnum[p] * pd.K,
+  GroupDesc gd = P->pgd[p];
+  gd.F[0] = P->Aw[fa];
+  gd.F[1] = P->Aw[fb];
+  FCTN_TIMED(P, FCTN_STAGE_PAIR, 2.0 * P->pnum[p] * gd.inner,
              (double)(P->fnum[fa] + P->fnum[fb] + P->pnum[p]) * P->es,
-             launch_pair(P->prec, pd, P->P[p], P->st));
+             launch_group(P->prec, gd, P->P[p], P->st));
   P->pvalid[p] = true;
   P->pver[p][0] = P->fver[fa];
   P->pver[p][1] = P->fver[fb];

@@ -192,105 +192,136 @@ hipError_t launch_build_basis(double* Q, double* Qt, double* lam_col, int32_t n,
 }
 
 // ---------------------------------------------------------------------------
-// Pair tensor of the reuse mechanism (two factors contracted over their
-// shared bond), written in the layout the sub-network generator reads.
-// ---------------------------------------------------------------------------
-// One output per thread, so that a wave's stores are contiguous; the pair
-// tensor and the factors stay below 2^31 elements (checked on the host), so
-// every index is 32-bit (64-bit division would dominate the kernel).
-template <typename T>
-__global__ void __launch_bounds__(256) pair_k(PairDesc pd, T* __restrict__ P, int64_t total) {
-  const T* Fa = (const T*)pd.Fa;
-  const T* Fb = (const T*)pd.Fb;
-  const uint32_t n = (uint32_t)total;
-  const uint32_t n2b = pd.n2b, n2a = pd.n2a, n1b = pd.n1b, n1a = pd.n1a, Ib = pd.Ib;
-  const int a_i = (int)pd.a_i, a_1 = (int)pd.a_1, a_2 = (int)pd.a_2, a_k = (int)pd.a_k;
-  const int b_i = (int)pd.b_i, b_1 = (int)pd.b_1, b_2 = (int)pd.b_2, b_k = (int)pd.b_k;
-  for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < n; o += gridDim.x * blockDim.x) {
-    uint32_t q = o;
-    const uint32_t b2 = q % n2b; q /= n2b;
-    const uint32_t a2 = q % n2a; q /= n2a;
-    const uint32_t b1 = q % n1b; q /= n1b;
-    const uint32_t a1 = q % n1a; q /= n1a;
-    const uint32_t ib = q % Ib, ia = q / Ib;
-    const T* pa = Fa + (int)ia * a_i + (int)a1 * a_1 + (int)a2 * a_2;
-    const T* pb = Fb + (int)ib * b_i + (int)b1 * b_1 + (int)b2 * b_2;
-    T acc = T(0);
-#pragma unroll 4
-    for (int k = 0; k < pd.K; ++k) acc += pa[k * a_k] * pb[k * b_k];
-    P[o] = acc;
-  }
-}
-
-hipError_t launch_pair(int prec, const PairDesc& pd, void* P, hipStream_t st) {
-  const int64_t total = (int64_t)pd.Ia * pd.Ib * pd.n1a * pd.n1b * pd.n2a * pd.n2b;
-  const int nb = (int)(cdiv(total, 256) < 8192 ? cdiv(total, 256) : 8192);
-  if (total == 0) return hipSuccess;
-  if (prec == P_F64)
-    pair_k<double><<<nb, 256, 0, st>>>(pd, (double*)P, total);
-  else
-    pair_k<float><<<nb, 256, 0, st>>>(pd, (float*)P, total);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Group operand (orders N >= 5): one thread per output entry decodes its
-// digits into member offsets, then walks the internal bonds as an odometer,
-// accumulating the product of the members' entries.  The group tensors are
-// small next to X (I_a I_b times a few hundred bond values), so this plain
-// form is HBM- and latency-bound, not a contraction worth MFMA tiles.
+// Cached sub-network operands: the pair tensors (N = 4) and the prefix and
+// suffix groups (N >= 5), each two members contracted over their shared
+// bonds.  For each outer index the entries form a block of sin consecutive
+// outputs.  One wave per workgroup, so that the many resident waves of a CU
+// work independently: it stages the member-0 rows [i0][t] and member-1 rows
+// [i1][t] the block reads (t padded with zeros to a multiple of 4) in LDS,
+// loading every member value once per block instead of once per output,
+// then forms the outputs from 16-byte LDS reads with contiguous stores.
+// `no` outer indices share one pass when the block is short.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) group_k(GroupDesc gd, T* __restrict__ G) {
-  // the member offsets of every internal bond value, once per workgroup
-  __shared__ int32_t tab[kGroupMaxInner * kGroupMaxMembers];
-  for (int t = threadIdx.x; t < gd.inner; t += blockDim.x) {
-    int32_t o[kGroupMaxMembers] = {0, 0, 0, 0, 0, 0};
-    uint32_t rem = (uint32_t)t;
-    for (int i = gd.ni - 1; i >= 0; --i) {
-      const uint32_t q = rem % (uint32_t)gd.isize[i];
-      rem /= (uint32_t)gd.isize[i];
-#pragma unroll
-      for (int f = 0; f < kGroupMaxMembers; ++f) {
-        o[f] += gd.imem0[i] == f ? (int32_t)q * gd.istr0[i] : 0;
-        o[f] += gd.imem1[i] == f ? (int32_t)q * gd.istr1[i] : 0;
+__global__ void __launch_bounds__(64) contract2_k(GroupDesc gd, T* __restrict__ G) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const T* F0 = (const T*)gd.F[0];
+  const T* F1 = (const T*)gd.F[1];
+  const int ip = gd.innerp, nin = gd.sin, n0 = gd.sin0, n1 = gd.sin1, no = gd.no;
+  T* A = (T*)smem_raw;                        // [no][n0][ip]
+  T* B = A + (size_t)no * n0 * ip;            // [no][n1][ip]
+  int32_t* tin = (int32_t*)(B + (size_t)no * n1 * ip);   // i0 | i1 << 16 per inner entry
+  int32_t* off0 = tin + nin;                  // member offsets of the inner digits
+  int32_t* off1 = off0 + n0;
+  int32_t* tt0 = off1 + n1;                   // member offsets of the internal bonds
+  int32_t* tt1 = tt0 + ip;
+  int32_t* base = tt1 + ip;                   // [no][2] outer offsets of this pass
+  const int lane = threadIdx.x;
+  // per-workgroup tables: the inner block's member index pairs and offsets
+  for (int i = lane; i < nin; i += 64) {
+    uint32_t rem = (uint32_t)i;
+    int32_t i0 = 0, i1 = 0, s0 = 1, s1 = 1, o0 = 0, o1 = 0;
+    for (int d = gd.nd - 1; d >= gd.ds; --d) {
+      const uint32_t sz = (uint32_t)gd.dsize[d];
+      const uint32_t quo = div_by(rem, gd.m_dsize[d]);
+      const int32_t q = (int32_t)(rem - quo * sz);
+      rem = quo;
+      if (gd.dmem[d] == 0) {
+        i0 += q * s0;
+        s0 *= (int32_t)sz;
+        o0 += q * gd.dstr[d];
+      } else {
+        i1 += q * s1;
+        s1 *= (int32_t)sz;
+        o1 += q * gd.dstr[d];
       }
     }
-#pragma unroll
-    for (int f = 0; f < kGroupMaxMembers; ++f) tab[t * kGroupMaxMembers + f] = o[f];
+    tin[i] = i0 | (i1 << 16);
+    // every member index combination occurs; write its offset once
+    if (i1 == 0) off0[i0] = o0;
+    if (i0 == 0) off1[i1] = o1;
   }
-  __syncthreads();
-  for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < gd.total;
-       e += gridDim.x * blockDim.x) {
-    int32_t off[kGroupMaxMembers] = {0, 0, 0, 0, 0, 0};
-    uint32_t rem = (uint32_t)e;
-    for (int d = gd.nd - 1; d >= 0; --d) {
-      const uint32_t sz = (uint32_t)gd.dsize[d];
-      const uint32_t q = rem % sz;
-      rem /= sz;
-      const int32_t add = (int32_t)q * gd.dstr[d];
-#pragma unroll
-      for (int f = 0; f < kGroupMaxMembers; ++f) off[f] += gd.dmem[d] == f ? add : 0;
+  for (int t = lane; t < ip; t += 64) {
+    int32_t o0 = 0, o1 = 0;
+    if (t < gd.inner) {
+      uint32_t rem = (uint32_t)t;
+      for (int i = gd.ni - 1; i >= 0; --i) {
+        const uint32_t sz = (uint32_t)gd.isize[i];
+        const int32_t q = (int32_t)(rem % sz);
+        rem /= sz;
+        o0 += q * gd.istr0[i];
+        o1 += q * gd.istr1[i];
+      }
     }
-    T acc = T(0);
-    for (int32_t t = 0; t < gd.inner; ++t) {
-      T prod = T(1);
-#pragma unroll
-      for (int f = 0; f < kGroupMaxMembers; ++f)
-        if (f < gd.nm) prod *= ((const T*)gd.F[f])[off[f] + tab[t * kGroupMaxMembers + f]];
-      acc += prod;
+    tt0[t] = o0;
+    tt1[t] = o1;
+  }
+  const int inner = gd.inner;
+  for (int64_t ob = (int64_t)blockIdx.x * no; ob < gd.nouter; ob += (int64_t)gridDim.x * no) {
+    const int nol = (int)(gd.nouter - ob < no ? gd.nouter - ob : no);
+    __syncthreads();   // tables written / the previous pass's LDS reads done
+    for (int ol = lane; ol < nol; ol += 64) {
+      uint32_t rem = (uint32_t)(ob + ol);
+      int32_t b0 = 0, b1 = 0;
+      for (int d = gd.ds - 1; d >= 0; --d) {
+        const uint32_t sz = (uint32_t)gd.dsize[d];
+        const int32_t a = (int32_t)(rem % sz) * gd.dstr[d];
+        rem /= sz;
+        if (gd.dmem[d] == 0) b0 += a; else b1 += a;
+      }
+      base[2 * ol] = b0;
+      base[2 * ol + 1] = b1;
     }
-    G[e] = acc;
+    __syncthreads();
+    // stage both members' rows of the nol outer indices (t-padding as zeros)
+    const int na = nol * n0 * ip, nb = nol * n1 * ip;
+    for (int j = lane; j < na + nb; j += 64) {
+      const bool m1 = j >= na;
+      const uint32_t jj = (uint32_t)(m1 ? j - na : j);
+      const uint32_t r = div_by(jj, gd.m_ip);            // r = ol * n + i
+      const int t = (int)(jj - r * ip);
+      const int nm = m1 ? n1 : n0;
+      const int ol = (int)div_by(r, m1 ? gd.m_n1 : gd.m_n0), i = (int)r - ol * nm;
+      T v = T(0);
+      if (t < inner)
+        v = m1 ? F1[base[2 * ol + 1] + off1[i] + tt1[t]] : F0[base[2 * ol] + off0[i] + tt0[t]];
+      (m1 ? B : A)[jj] = v;
+    }
+    __syncthreads();
+    const int ne = nol * nin;
+    T* out = G + ob * nin;
+    for (int e = lane; e < ne; e += 64) {
+      const int ol = (int)div_by((uint32_t)e, gd.m_nin), i = e - ol * nin;
+      const int32_t pr = tin[i];
+      const T* a = A + ((size_t)ol * n0 + (pr & 0xffff)) * ip;
+      const T* b = B + ((size_t)ol * n1 + (pr >> 16)) * ip;
+      T acc = T(0);
+      for (int t = 0; t < ip; t += 4) {
+        if constexpr (sizeof(T) == 4) {
+          const f32x4 x = *(const f32x4*)(a + t), y = *(const f32x4*)(b + t);
+          acc += x[0] * y[0];
+          acc += x[1] * y[1];
+          acc += x[2] * y[2];
+          acc += x[3] * y[3];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc += a[t + q] * b[t + q];
+        }
+      }
+      out[e] = acc;
+    }
   }
 }
 
 hipError_t launch_group(int prec, const GroupDesc& gd, void* G, hipStream_t st) {
   if (gd.total == 0) return hipSuccess;
-  const int nb = (int)(cdiv(gd.total, 256) < 8192 ? cdiv(gd.total, 256) : 8192);
+  // enough single-wave workgroups for 24 per CU, each over several passes
+  const int64_t passes = (gd.nouter + gd.no - 1) / gd.no;
+  const int nb = (int)(passes < 6144 ? passes : 6144);
   if (prec == P_F64)
-    group_k<double><<<nb, 256, 0, st>>>(gd, (double*)G);
+    contract2_k<double><<<nb, 64, gd.lds_bytes, st>>>(gd, (double*)G);
   else
-    group_k<float><<<nb, 256, 0, st>>>(gd, (float*)G);
+    contract2_k<float><<<nb, 64, gd.lds_bytes, st>>>(gd, (float*)G);
   return hipGetLastError();
 }
 

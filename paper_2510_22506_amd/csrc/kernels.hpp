@@ -78,36 +78,43 @@ struct RecGeom {
   size_t lds_bytes;
 };
 
-// pair tensor P[(ia, ib)][(a1, b1)][(a2, b2)] = sum_kap Fa[ia, a1, a2, kap] Fb[ib, b1, b2, kap]
-struct PairDesc {
-  const void* Fa;
-  int64_t a_i, a_1, a_2, a_k;
-  const void* Fb;
-  int64_t b_i, b_1, b_2, b_k;
-  int32_t Ia, Ib, n1a, n2a, n1b, n2b, K;
-};
-
 // precision codes shared with the C ABI
 enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
 
-// Sub-network operand for orders N >= 5: the contraction of a group of
-// consecutive factors over the bonds inside the group,
-//   G[d_0, .., d_{nd-1}] = sum over the internal bonds of prod_f F_f[off_f],
+// Cached sub-network operand (the N = 4 pair tensors and the N >= 5 prefix
+// and suffix groups): two members contracted over the bonds they share,
+//   G[d_0, .., d_{nd-1}] = sum_t F_0[off_0 + t0(t)] F_1[off_1 + t1(t)],
 // where output digit d (last fastest) adds d * dstr[d] to member dmem[d]'s
-// offset and internal digit i adds i * istr0[i] to member imem0[i] and
-// i * istr1[i] to member imem1[i] (a bond joins two members).  All offsets
-// and the entry count fit 31 bits (checked at plan time).
-constexpr int kGroupMaxMembers = 6;
+// offset and internal digit i adds i * istr0[i] to member 0's and
+// i * istr1[i] to member 1's.  All offsets and the entry count fit 31 bits
+// (checked at plan time).
+//
+// Launch shape (set on the host): the digits from `ds` on are the inner
+// block, `sin` consecutive entries made of `sin0` member-0 and `sin1`
+// member-1 index combinations; a wave takes `no` outer indices at a time,
+// stages their member-0 rows [i0][t] and member-1 rows [i1][t] (t padded to
+// `innerp`) in LDS, then writes the no * sin entries.  Every quotient the
+// kernel forms inside a block is below 2^16 and uses the multipliers m_*.
 constexpr int kGroupMaxDigits = 16;
 constexpr int kGroupMaxInner = 1024;   // internal bond values per entry
+constexpr int kGroupMaxLds = 32 * 1024;
 struct GroupDesc {
-  const void* F[kGroupMaxMembers];
+  const void* F[2];
   int32_t dsize[kGroupMaxDigits], dmem[kGroupMaxDigits], dstr[kGroupMaxDigits];
-  int32_t isize[kGroupMaxDigits], imem0[kGroupMaxDigits], istr0[kGroupMaxDigits];
-  int32_t imem1[kGroupMaxDigits], istr1[kGroupMaxDigits];
-  int32_t nm, nd, ni;
+  int32_t isize[kGroupMaxDigits], istr0[kGroupMaxDigits], istr1[kGroupMaxDigits];
+  uint64_t m_dsize[kGroupMaxDigits];   // for the inner digits
+  uint64_t m_ip, m_n0, m_n1, m_nin;
+  int32_t nd, ni;
   int32_t total, inner;   // output entries, terms per entry
+  int32_t ds, sin, sin0, sin1, innerp, no, nouter;
+  int32_t lds_bytes;
 };
+
+// x / d exactly for x, d < 2^16 (x * d < 2^32): (x * ceil(2^32 / d)) >> 32
+inline uint64_t div_magic(uint32_t d) { return ((1ull << 32) + d - 1) / d; }
+__device__ inline uint32_t div_by(uint32_t x, uint64_t m) {
+  return (uint32_t)(((uint64_t)x * m) >> 32);
+}
 
 // one factor's shapes before and after a rank growth (last mode fastest);
 // bit j of zero_modes: new indices along mode j give zero entries
@@ -139,7 +146,6 @@ hipError_t launch_cast_factor(int prec, const double* A64, void* Aw, void* Au, i
                               int32_t s, int64_t spost, hipStream_t st);
 hipError_t launch_build_basis(double* Q, double* Qt, double* lam_col, int32_t n, double delta,
                               hipStream_t st);
-hipError_t launch_pair(int prec, const PairDesc& pd, void* P, hipStream_t st);
 hipError_t launch_group(int prec, const GroupDesc& gd, void* G, hipStream_t st);
 hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView& xv,
                            const GramGeom& g, void* part, hipStream_t st);
