@@ -165,8 +165,21 @@ fctn_status fctn_set_factors_dev(fctn_plan_t plan, const double* A_dev);
 fctn_status fctn_set_observed(fctn_plan_t plan, const void* Y_dev,
                               const uint8_t* mask_dev);
 
-/* Overwrite X (elem tensor on the device); for step-level checks. */
+/* Overwrite X (elem tensor on the device); for step-level checks and for
+ * resuming a run. */
 fctn_status fctn_set_x(fctn_plan_t plan, const void* X_dev);
+
+/* Checkpoint and resume.  The sweep index t is the number of sweeps the run
+ * has done; it selects the next sweep's factor order (the alternating order
+ * of Section 3.3 for N = 4).  A run's state is X (fctn_get_x), the float64
+ * factors (fctn_get_factor) and t: a plan with the same descriptor that is
+ * given them (fctn_set_x, fctn_set_factors or fctn_set_factors_dev, then
+ * fctn_set_sweep_index) after fctn_set_observed continues the run bit for
+ * bit.  fctn_set_sweep_index also restarts the per-sweep history at t
+ * (fctn_get_history then serves sweeps t and later).  t < 0 is
+ * FCTN_E_INVALID. */
+fctn_status fctn_get_sweep_index(fctn_plan_t plan, int64_t* t_host);
+fctn_status fctn_set_sweep_index(fctn_plan_t plan, int64_t t);
 
 /* Rank growth (Algorithms 1-2 start from rank ones and grow to the maximal
  * FCTN-rank; the growth rule is deferred to the paper's reference [Zheng2022]).

@@ -123,6 +123,7 @@ struct fctn_plan_s {
   GroupSlot grp[kMaxGroups];   // orders N >= 5
   int ngrp;
   int64_t sweeps_done;
+  int64_t hist_first;  // first sweep index whose history this plan holds
   int64_t fver[FCTN_MAX_ORDER];
   int64_t pver[2][2];
   bool pvalid[2];
@@ -1346,6 +1347,20 @@ fctn_status fctn_set_x(fctn_plan_t P, const void* X_dev) {
   return FCTN_OK;
 }
 
+fctn_status fctn_get_sweep_index(fctn_plan_t P, int64_t* t_host) {
+  if (!P || !t_host) return FCTN_E_INVALID;
+  *t_host = P->sweeps_done;
+  return FCTN_OK;
+}
+
+fctn_status fctn_set_sweep_index(fctn_plan_t P, int64_t t) {
+  if (!P || t < 0) return FCTN_E_INVALID;
+  if (P->sticky != FCTN_OK) return P->sticky;
+  P->sweeps_done = t;
+  P->hist_first = t;
+  return FCTN_OK;
+}
+
 fctn_status fctn_regrow(fctn_plan_t to, fctn_plan_t from, const double* fill_dev) {
   if (!to || !from || !fill_dev || to == from) return FCTN_E_INVALID;
   if (to->sticky != FCTN_OK) return to->sticky;
@@ -1405,7 +1420,7 @@ fctn_status fctn_sweep(fctn_plan_t P, int32_t nsweeps, fctn_sweep_stats* stats_h
     if (s != FCTN_OK) return s;
   }
   if (stats_host) {
-    if (P->sweeps_done == 0) {
+    if (P->sweeps_done == P->hist_first) {
       memset(stats_host, 0, sizeof(*stats_host));
       return FCTN_OK;
     }
@@ -1539,7 +1554,8 @@ fctn_status fctn_get_history(fctn_plan_t P, int32_t first, int32_t count,
                              fctn_sweep_stats* out_host) {
   if (!P || !out_host || first < 0 || count < 0) return FCTN_E_INVALID;
   if (P->sticky != FCTN_OK) return P->sticky;
-  if ((int64_t)first + count > P->sweeps_done || P->sweeps_done - first > kHist)
+  if ((int64_t)first + count > P->sweeps_done || P->sweeps_done - first > kHist ||
+      first < P->hist_first)
     return FCTN_E_INVALID;
   std::vector<double> h((size_t)kHist * 4);
   if (hipMemcpyAsync(h.data(), P->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost,

@@ -101,6 +101,8 @@ _SIGS = {
     "fctn_set_observed": (ctypes.c_int, [_P, _P, _P]),
     "fctn_set_factors_dev": (ctypes.c_int, [_P, _P]),
     "fctn_set_x": (ctypes.c_int, [_P, _P]),
+    "fctn_get_sweep_index": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "fctn_set_sweep_index": (ctypes.c_int, [_P, ctypes.c_int64]),
     "fctn_regrow": (ctypes.c_int, [_P, _P, _P]),
     "fctn_sweep": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(fctn_sweep_stats)]),
     "fctn_sweep_many": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32]),
@@ -306,6 +308,39 @@ class Plan:
         _check(lib().fctn_get_x(self.handle, _ptr(out)), "fctn_get_x")
         self.stream.synchronize()
         return out
+
+    @property
+    def sweep_index(self):
+        t = ctypes.c_int64()
+        _check(lib().fctn_get_sweep_index(self.handle, ctypes.byref(t)), "fctn_get_sweep_index")
+        return t.value
+
+    def set_sweep_index(self, t):
+        _check(lib().fctn_set_sweep_index(self.handle, int(t)), "fctn_set_sweep_index")
+
+    # -- checkpoint / resume --------------------------------------------------
+    def save_state(self, path):
+        """Write the run's state (X, the float64 factors, the sweep index) and
+        the shape it belongs to to an .npz file (no pickled objects)."""
+        arrs = {"X": self.x().cpu().numpy(), "t": np.int64(self.sweep_index),
+                "dims": np.asarray(self.dims, dtype=np.int64),
+                "ranks": np.asarray(self.ranks, dtype=np.int64),
+                "precision": np.asarray(self.precision)}
+        for k in range(len(self.dims)):
+            arrs["A%d" % k] = self.factor(k).cpu().numpy()
+        np.savez(path, **arrs)
+
+    def load_state(self, path):
+        """Resume a run saved by save_state on a plan with the same descriptor
+        (call after set_observed, which resets X)."""
+        with np.load(path, allow_pickle=False) as f:
+            if tuple(f["dims"]) != self.dims or tuple(f["ranks"]) != self.ranks or \
+                    str(f["precision"]) != self.precision:
+                raise FctnError(E_INVALID, "load_state: the state is of another problem shape")
+            self.set_factors([f["A%d" % k] for k in range(len(self.dims))])
+            self.set_x(f["X"])
+            self.set_sweep_index(int(f["t"]))
+        self.stream.synchronize()
 
     def factor(self, k):
         shape = factor_shape(self.dims, self.ranks, k)

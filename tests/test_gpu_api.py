@@ -8,7 +8,9 @@
 * fctn_complete with tol = 0 runs exactly max_sweeps sweeps;
 * fctn_sweep_many over plans of different orders and precisions on distinct
   streams gives each plan the result of fctn_sweep on that plan alone, bit
-  for bit.
+  for bit;
+* a run checkpointed (X, float64 factors, sweep index) and resumed on a new
+  plan continues bit for bit.
 """
 
 import numpy as np
@@ -139,3 +141,35 @@ def test_sweep_stats_stage_times():
         assert v <= prof[stage]["ms"] * (1 + 1e-6) + 1e-6, (stage, v, prof[stage]["ms"])
     h = p.history(0, 3)
     assert all(all(v == 0.0 for v in e["ms_stage"].values()) for e in h)
+
+
+@pytest.mark.parametrize("name,dims,prec", [("c3", (16, 18, 3, 6), "f32"),
+                                            ("c7", (6, 5, 4, 3, 7), "bf16x3")])
+def test_checkpoint_resume_bitwise(tmp_path, name, dims, prec):
+    # a run saved after 3 sweeps (an odd sweep index: the next order-4 sweep
+    # takes the permuted order) and resumed on a new plan continues the run
+    # bit for bit: X, factors and the resumed sweeps' scalars
+    prob = make_problem(name, seed=14, dims=dims, precision="f32", sr=0.2)
+    straight = _plan(prob, prec)
+    straight.sweep(7)
+    h_straight = straight.history(3, 4)
+    first = _plan(prob, prec)
+    first.sweep(3)
+    path = str(tmp_path / "state.npz")
+    first.save_state(path)
+    first.close()
+    resumed = _plan(prob, prec)
+    resumed.load_state(path)
+    assert resumed.sweep_index == 3
+    resumed.sweep(4)
+    assert resumed.sweep_index == 7
+    np.testing.assert_array_equal(resumed.x().cpu().numpy(), straight.x().cpu().numpy())
+    for k in range(len(dims)):
+        np.testing.assert_array_equal(resumed.factor(k).cpu().numpy(),
+                                      straight.factor(k).cpu().numpy())
+    h = resumed.history(3, 4)
+    for a, b in zip(h, h_straight):
+        assert a["rel_change"] == b["rel_change"] and a["objective"] == b["objective"]
+    from paper_2510_22506_amd.fctn import FctnError
+    with pytest.raises(FctnError):
+        resumed.history(2, 1)      # before the resumed run's first sweep
