@@ -46,7 +46,9 @@ def build(verbose=False):
     with concurrent.futures.ThreadPoolExecutor(workers) as ex:
         list(ex.map(_run, [cmd for _, cmd in jobs]))
     tmp = LIB + ".tmp"
-    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in jobs], "-o", tmp])
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(hipcc))), "lib")
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in jobs],
+          "-L", rocm_lib, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + rocm_lib, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

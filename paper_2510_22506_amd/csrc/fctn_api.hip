@@ -15,6 +15,8 @@
 #include <new>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "fctn.h"
 #include "kernels.hpp"
 
@@ -1076,18 +1078,34 @@ void sweep_order(const fctn_plan_s* P, int64_t t, int* order) {
   }
 }
 
+// host-side ranges for rocprofv3 --marker-trace: one per sweep and one per
+// factor block inside it (no cost without a profiler attached)
+struct Range {
+  explicit Range(const char* m) { roctxRangePushA(m); }
+  ~Range() { roctxRangePop(); }
+};
+const char* const kModeRange[FCTN_MAX_ORDER] = {"fctn factor 1", "fctn factor 2", "fctn factor 3",
+                                                "fctn factor 4", "fctn factor 5", "fctn factor 6",
+                                                "fctn factor 7", "fctn factor 8"};
+
 fctn_status one_sweep(fctn_plan_s* P) {
+  Range sweep_range("fctn sweep");
   int order[FCTN_MAX_ORDER];
   sweep_order(P, P->sweeps_done, order);
   fctn_status s;
   for (int n = 0; n < P->N; ++n) {
     const int k = order[n];
+    Range mode_range(kModeRange[k]);
     if ((s = gram_rhs(P, k, P->G, P->B)) != FCTN_OK) return s;
     if ((s = solve(P, k, P->G, P->B)) != FCTN_OK) return s;
   }
   const int last = order[P->N - 1];
-  if ((s = reconstruct(P, last, P->Z)) != FCTN_OK) return s;
-  if ((s = x_update(P, P->Z, P->hist + (P->sweeps_done % kHist) * 4, true)) != FCTN_OK) return s;
+  {
+    Range x_range("fctn X step");
+    if ((s = reconstruct(P, last, P->Z)) != FCTN_OK) return s;
+    if ((s = x_update(P, P->Z, P->hist + (P->sweeps_done % kHist) * 4, true)) != FCTN_OK)
+      return s;
+  }
   P->sweeps_done++;
   return FCTN_OK;
 }
