@@ -116,6 +116,56 @@ __device__ inline void gather2d(int x0, int sx, int nx, int y0, int sy, int ny, 
   }
 }
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+constexpr int kDmaMinRun = 32;   // shortest LDS row the small-tile kernel copies by DMA
+
+// The same slab with global-to-LDS copies (float32): lane l of a copy writes
+// the l-th of 64 consecutive LDS values, so a copy moves 64 values without
+// holding registers and a wave issues its copies back to back.  [p][kap]:
+// one row p per wave at a time, lanes along kap; [kap][p]: lanes along p (the
+// lane's table entry read once per 64-row chunk), one kap row per copy.
+// Padding (kap >= K) and rows beyond the tensor edge are zeroed with
+// ordinary stores.
+__device__ inline void stage_slab_dma(const float* __restrict__ F, int64_t base, int64_t f_k,
+                                      int K, int Kp, int Pp, int s_k, int s_p,
+                                      const SlabRow* __restrict__ tab, int64_t lim,
+                                      float* __restrict__ S, int lane, int wave, int nw) {
+  const float* Fb = F + base;
+  if (s_k == 1) {                       // [p][kap]
+    for (int p = wave; p < Pp; p += nw) {
+      const SlabRow r = tab[p];
+      float* row = S + p * s_p;
+      if (r.cl < lim) {
+        const float* src = Fb + r.off;
+        for (int k0 = 0; k0 < K; k0 += 64)
+          if (k0 + lane < K)
+            __builtin_amdgcn_global_load_lds((const void*)(src + (int64_t)(k0 + lane) * f_k),
+                                             (lds_void_t*)(row + k0), 4, 0, 0);
+        for (int k = K + lane; k < Kp; k += 64) row[k] = 0.f;
+      } else {
+        for (int k = lane; k < Kp; k += 64) row[k] = 0.f;
+      }
+    }
+  } else {                              // [kap][p]
+    for (int p0 = 0; p0 < Pp; p0 += 64) {
+      const int p = p0 + lane;
+      const bool real = p < Pp;
+      SlabRow r{0, 0, 0};
+      if (real) r = tab[p];
+      const bool ok = real && r.cl < lim;
+      const float* src = Fb + r.off;
+      for (int k = wave; k < Kp; k += nw) {
+        float* row = S + k * s_k;
+        if (ok && k < K)
+          __builtin_amdgcn_global_load_lds((const void*)(src + (int64_t)k * f_k),
+                                           (lds_void_t*)(row + p0), 4, 0, 0);
+        else if (real)
+          row[p] = 0.f;
+      }
+    }
+  }
+}
+
 // Stage one operand slab S(kap, p) = F[tab[p].off + base + kap * f_k] (zero
 // in the padding and beyond the tensor edge: tab[p].cl >= lim).  Lanes run
 // along the slab's contiguous index (2^lw of them).  kBatched: loads issued in
@@ -232,21 +282,36 @@ __device__ inline void mgen_mfma(const TileGeom& tg, const T* __restrict__ Us,
                      nwaves);
 }
 
-template <typename T, bool kBatched, bool kVec = false>
+template <typename T, bool kBatched, bool kVec = false, bool kDmaStage = false>
 __device__ inline void stage_operands(const MGen& mg, const TileGeom& tg, const T* U, const T* V,
                                       int64_t tu, int64_t tv, int64_t& cur_tu, int64_t& cur_tv,
                                       T* Us, T* Vs, const SlabRow* ptab, const SlabRow* qtab,
                                       int tid, int nth) {
+  // the float32 Gram kernels stage by global-to-LDS copies: the general
+  // one always (its register path holds one load per thread), the
+  // small-tile one where the slab's LDS rows are long enough to keep most of
+  // a copy's 64 lanes busy (its batched register path is better otherwise)
+  constexpr bool kDma = sizeof(T) == 4 && kDmaStage;
   if (tu != cur_tu) {
     const int64_t cu0 = tu * tg.TCu;
-    stage_slab<T, kBatched, kVec>(U, cu0 * mg.u_cu, mg.u_k, mg.K, tg.Kp, tg.Pp, tg.us_k, tg.us_p, tg.u_lw,
-                            tg.u_vec != 0, ptab, mg.Cu - cu0, Us, tid, nth);
+    if (kDma && (!kBatched || (tg.us_k == 1 ? mg.K : tg.Pp) >= kDmaMinRun))
+      stage_slab_dma((const float*)U, cu0 * mg.u_cu, mg.u_k, mg.K, tg.Kp, tg.Pp, tg.us_k, tg.us_p,
+                     ptab, mg.Cu - cu0, (float*)Us, tid & 63, tid >> 6, nth >> 6);
+    else
+      stage_slab<T, kBatched, kVec>(U, cu0 * mg.u_cu, mg.u_k, mg.K, tg.Kp, tg.Pp, tg.us_k,
+                                    tg.us_p, tg.u_lw, tg.u_vec != 0, ptab, mg.Cu - cu0, Us, tid,
+                                    nth);
     cur_tu = tu;
   }
   if (tv != cur_tv) {
     const int64_t cv0 = tv * tg.TCv;
-    stage_slab<T, kBatched, kVec>(V, cv0 * mg.v_cv, mg.v_k, mg.K, tg.Kp, tg.Qp, tg.vs_k, tg.vs_q, tg.v_lw,
-                            tg.v_vec != 0, qtab, mg.Cv - cv0, Vs, tid, nth);
+    if (kDma && (!kBatched || (tg.vs_k == 1 ? mg.K : tg.Qp) >= kDmaMinRun))
+      stage_slab_dma((const float*)V, cv0 * mg.v_cv, mg.v_k, mg.K, tg.Kp, tg.Qp, tg.vs_k, tg.vs_q,
+                     qtab, mg.Cv - cv0, (float*)Vs, tid & 63, tid >> 6, nth >> 6);
+    else
+      stage_slab<T, kBatched, kVec>(V, cv0 * mg.v_cv, mg.v_k, mg.K, tg.Kp, tg.Qp, tg.vs_k,
+                                    tg.vs_q, tg.v_lw, tg.v_vec != 0, qtab, mg.Cv - cv0, Vs, tid,
+                                    nth);
     cur_tv = tv;
   }
 }
@@ -255,10 +320,12 @@ __device__ inline void stage_operands(const MGen& mg, const TileGeom& tg, const 
 // stages its next tile while the other runs MFMA (float64 keeps one per CU).
 // TPW output tiles per wave: 16 in general; 2 for the modes with at most 16
 // output tiles (small s_k), whose freed accumulator registers let the operand
-// and X staging keep kGatherBatch loads in flight per thread.  VEC: the
-// instance with 16-byte staging of [kap][p] slabs, kept separate because its
-// extra code raises the kernel's register spills.
-template <typename T, int TPW, bool VEC = false, int NW = kGramWaves>
+// and X staging keep kGatherBatch loads in flight per thread.  The general
+// float32 instance stages the operand slabs and the X block by global-to-LDS
+// copies instead: every wave issues its copies back to back with no
+// registers held (at 128 VGPRs it can keep only one ordinary load in flight
+// per thread), and the barrier after staging waits for all of them.
+template <typename T, int TPW, int NW = kGramWaves>
 __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MGen mg, const T* __restrict__ X,
                                                            XView xv, GramGeom g,
                                                            T* __restrict__ part) {
@@ -340,15 +407,41 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
   FCTN_GRAM_MARK_INIT
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
-    stage_operands<T, kBatch, VEC>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
-                              (64 * NW));
+    stage_operands<T, kBatch, false, true>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab,
+                                           qtab, tid, (64 * NW));
     FCTN_GRAM_MARK(0);
     if (xrows > 0) {
       const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
       const int64_t lim_u = mg.Cu - cu0, lim_v = mg.Cv - cv0;
       const T* xb = X + cu0 * xv.x_cu + cv0 * xv.x_cv + (int64_t)(ba_lo * 16) * xv.x_ik;
       const int xlim = xv.Ik - ba_lo * 16;
-      if constexpr (kBatch) {
+      if constexpr (sizeof(T) == 4) {
+        // global-to-LDS copies: wave w takes rows w, w + NW, ..; lane l of a
+        // copy writes column c0 + l of its row, so one instruction moves 64
+        // values with no registers held.  Columns past the tensor edge are
+        // skipped: their M columns are zero, so the (finite) values the
+        // buffer holds there add nothing; rows past I_k only feed outputs
+        // that are discarded.
+        // Each lane's column (its table entry) is read once per 64-column
+        // chunk, outside the row loop, so the copies issue back to back.
+        const int rend = min(xrows, xlim);
+        for (int c0 = 0; c0 < tg.tcol; c0 += 64) {
+          const int c = c0 + lane;
+          bool okc = false;
+          int64_t off = 0;
+          if (c < tg.tcol) {
+            const SlabRow cr = ctab[c];
+            okc = cr.cl < lim_u && cr.map < lim_v;
+            off = cr.off;
+          }
+          if (okc) {
+            const T* xc = xb + off;
+            for (int r = wave; r < rend; r += NW)
+              __builtin_amdgcn_global_load_lds((const void*)(xc + (int64_t)r * xv.x_ik),
+                                               (lds_void_t*)(Xs + r * ldx + c0), 4, 0, 0);
+          }
+        }
+      } else if constexpr (kBatch) {
         // thread (c, r0): column c, rows r0, r0 + ngrp, ...
         const int ngrp = (64 * NW) / tg.tcol;
         if (tid < ngrp * tg.tcol) {
@@ -744,14 +837,10 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
       }
     } else if (small) {
       run(gram_rhs_k<float, 2>, kGramThreads);
-    } else if (g.tg.u_vec || g.tg.v_vec) {
-      // a separate instance, so that the 16-byte staging code does not cost
-      // the other modes' kernel registers
-      if (wide) run(gram_rhs_k<float, T2, true, W2>, 2 * kGramThreads);
-      else run(gram_rhs_k<float, kTPW, true>, kGramThreads);
     } else {
-      if (wide) run(gram_rhs_k<float, T2, false, W2>, 2 * kGramThreads);
-      else run(gram_rhs_k<float, kTPW>, kGramThreads);
+      // the general instance stages its operands and X by global-to-LDS
+      // copies, whatever the slab layout
+      run(gram_rhs_k<float, kTPW>, kGramThreads);
     }
   }
   return hipGetLastError();
