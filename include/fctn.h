@@ -54,7 +54,8 @@ typedef enum {
   FCTN_E_NOMEM = 2,        /* workspace smaller than fctn_workspace_bytes */
   FCTN_E_DEVICE = 3,       /* a HIP runtime call failed                   */
   FCTN_E_NUMERIC = 4,      /* non-finite observed value on Omega          */
-  FCTN_E_UNSUPPORTED = 5   /* valid for the method, not supported here    */
+  FCTN_E_UNSUPPORTED = 5,  /* valid for the method, not supported here    */
+  FCTN_E_CANCELLED = 6     /* a served request cancelled by the caller    */
 } fctn_status;
 
 typedef enum {
@@ -315,7 +316,8 @@ typedef struct {
   int32_t status;           /* FCTN_OK; FCTN_E_NUMERIC: a non-finite
                                observed value (the sweeps still ran);
                                FCTN_E_DEVICE: a kernel's bounded wait gave
-                               up, the result is invalid                      */
+                               up, the result is invalid; FCTN_E_CANCELLED:
+                               fctn_server_cancel stopped it (see there)     */
   int32_t sweeps_done;
   double rel_change;        /* of the last sweep (eq. 10 stopping quantity)   */
   double objective;         /* f after the last sweep (Section 3.5)           */
@@ -341,6 +343,16 @@ fctn_status fctn_server_submit(fctn_server_t server, const fctn_request* req);
  * and queue further sweeps of the admitted ones. */
 fctn_status fctn_server_step(fctn_server_t server, fctn_completion* done,
                              int32_t max_done, int32_t* n_done);
+
+/* Cancel the request with this tag.  A queued request is dropped: its
+ * completion (FCTN_E_CANCELLED, sweeps_done 0, X_out untouched) comes with
+ * the next fctn_server_step.  A resident request queues no further sweeps:
+ * once the sweeps already queued have run, X_out receives X after them and
+ * the completion reports FCTN_E_CANCELLED with that sweep count and its
+ * scalars (unless a device error takes precedence).  FCTN_E_INVALID if no
+ * queued or resident request that is still sweeping has the tag (the first
+ * one found is cancelled when tags repeat). */
+fctn_status fctn_server_cancel(fctn_server_t server, uint64_t tag);
 
 /* Queue length, resident requests and arena bytes in use (any may be NULL). */
 fctn_status fctn_server_query(fctn_server_t server, int32_t* queued,

@@ -1720,6 +1720,7 @@ const char* fctn_status_str(fctn_status s) {
     case FCTN_E_DEVICE: return "HIP runtime error";
     case FCTN_E_NUMERIC: return "non-finite observed value";
     case FCTN_E_UNSUPPORTED: return "unsupported configuration";
+    case FCTN_E_CANCELLED: return "cancelled";
   }
   return "unknown status";
 }
@@ -1750,6 +1751,7 @@ struct SrvPending {
 struct SrvSlot {
   bool busy = false;
   bool finishing = false;
+  bool cancelled = false;
   fctn_plan_s* plan = nullptr;
   size_t off = 0, bytes = 0;
   int32_t enq = 0;
@@ -1771,6 +1773,7 @@ struct fctn_server_s {
   int depth = 1;
   std::vector<SrvSlot> slots;
   std::deque<SrvPending> queue;
+  std::deque<fctn_completion> dropped;   // cancelled before admission
   std::vector<hipEvent_t> pool;
   int32_t* pin_flag = nullptr;  // pinned host memory, two flags per slot: the
                                 // non-finite flag of Y and the device error word
@@ -1931,6 +1934,11 @@ fctn_status fctn_server_step(fctn_server_t S, fctn_completion* done, int32_t max
   *n_done = 0;
   if (S->sticky != FCTN_OK) return S->sticky;
   const int ns = (int)S->slots.size();
+  // requests cancelled while queued
+  while (!S->dropped.empty() && *n_done < max_done) {
+    done[(*n_done)++] = S->dropped.front();
+    S->dropped.pop_front();
+  }
   // retire
   for (int i = 0; i < ns && *n_done < max_done; ++i) {
     SrvSlot& sl = S->slots[i];
@@ -1941,7 +1949,9 @@ fctn_status fctn_server_step(fctn_server_t S, fctn_completion* done, int32_t max
     fctn_completion& c = done[(*n_done)++];
     c.tag = sl.req.tag;
     c.status = S->pin_flag[2 * i + 1] ? FCTN_E_DEVICE
-               : S->pin_flag[2 * i] ? FCTN_E_NUMERIC : FCTN_OK;
+               : sl.cancelled          ? FCTN_E_CANCELLED
+               : S->pin_flag[2 * i]    ? FCTN_E_NUMERIC
+                                       : FCTN_OK;
     c.sweeps_done = sl.enq;
     c.rel_change = S->pin_stats[4 * i + 0];
     c.objective = S->pin_stats[4 * i + 3];
@@ -1955,7 +1965,7 @@ fctn_status fctn_server_step(fctn_server_t S, fctn_completion* done, int32_t max
     delete sl.plan;
     sl.plan = nullptr;
     arena_free(S, sl.off, sl.bytes);
-    sl.busy = sl.finishing = false;
+    sl.busy = sl.finishing = sl.cancelled = false;
   }
   // admit, first in first out: the head of the queue waits for room
   while (!S->queue.empty()) {
@@ -2009,6 +2019,31 @@ fctn_status fctn_server_step(fctn_server_t S, fctn_completion* done, int32_t max
     }
   }
   return FCTN_OK;
+}
+
+fctn_status fctn_server_cancel(fctn_server_t S, uint64_t tag) {
+  if (!S) return FCTN_E_INVALID;
+  if (S->sticky != FCTN_OK) return S->sticky;
+  for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
+    if (it->r.tag != tag) continue;
+    fctn_completion c{};
+    c.tag = tag;
+    c.status = FCTN_E_CANCELLED;
+    c.t_submit = it->t_submit;
+    c.t_done = mono_now();
+    S->dropped.push_back(c);
+    S->queue.erase(it);
+    return FCTN_OK;
+  }
+  for (SrvSlot& sl : S->slots) {
+    if (!sl.busy || sl.finishing || sl.cancelled || sl.req.tag != tag) continue;
+    // no further sweeps: fctn_server_step finishes it once the queued ones
+    // have run (or at once if none was queued yet)
+    sl.cancelled = true;
+    sl.req.sweeps = sl.enq;
+    return FCTN_OK;
+  }
+  return FCTN_E_INVALID;
 }
 
 fctn_status fctn_server_query(fctn_server_t S, int32_t* queued, int32_t* active,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfctn.so")
 FCTN_MAX_ORDER = 8
 FCTN_MAX_BONDS = 28
 
-OK, E_INVALID, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = range(6)
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED, E_CANCELLED = range(7)
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 
 
@@ -128,6 +128,7 @@ _SIGS = {
     "fctn_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(fctn_request)]),
     "fctn_server_step": (ctypes.c_int, [_P, ctypes.POINTER(fctn_completion), ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int32)]),
+    "fctn_server_cancel": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "fctn_server_query": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_size_t)]),
@@ -492,6 +493,12 @@ class Server:
             c = self._done[i].as_dict()
             out.append((c, self.keep.pop(c["tag"])[3]))
         return out
+
+    def cancel(self, tag):
+        """Cancel a queued or resident request (fctn_server_cancel); its
+        completion, status E_CANCELLED, comes from a later step()."""
+        _check(lib().fctn_server_cancel(self.handle, ctypes.c_uint64(int(tag))),
+               "fctn_server_cancel")
 
     def query(self):
         q = ctypes.c_int32()

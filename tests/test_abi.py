@@ -34,8 +34,8 @@ def test_exports_every_declared_symbol(F):
 
 
 def test_status_strings(F):
-    for s in range(6):
-        assert F.fctn_status_str(s)
+    for s in range(7):
+        assert F.fctn_status_str(s) and F.fctn_status_str(s) != 'unknown status'
 
 
 def test_workspace_bytes_and_validation(F):

@@ -4,7 +4,9 @@ state and every kernel is deterministic), for orders 3, 4 and 5, four
 precisions and the asymmetric extrapolation; the float64 requests in the mix
 match the oracle; a small arena still admits every request by footprint;
 a request larger than the arena is rejected; a non-finite observed value is
-reported on the completion."""
+reported on the completion; a cancelled request completes as cancelled,
+queued ones at once and resident ones after the sweeps already queued, whose
+X equals a plan run alone for that many sweeps."""
 
 import numpy as np
 import pytest
@@ -132,3 +134,36 @@ def test_nonfinite_observed_value_is_flagged():
     finally:
         srv.close()
     assert res["done"][r["tag"]][0]["status"] == fctn.E_NUMERIC
+
+
+def test_cancel_queued_and_resident_requests():
+    reqs = [_request(70 + i, "c3", (12, 10, 3, 5), (4, 2, 3, 2, 3, 2), "f32", sweeps=8)[1]
+            for i in range(3)]
+    srv = fctn.Server(arena_bytes=64 << 20, nstreams=1, max_active=1, depth=1)
+    done = {}
+    try:
+        for r in reqs:
+            srv.submit(**r)
+        for c, X in srv.step():          # the first request is admitted
+            done[c["tag"]] = (c, X)
+        q, a, _ = srv.query()
+        assert (q, a) == (2, 1)
+        srv.cancel(reqs[1]["tag"])       # queued
+        srv.cancel(reqs[0]["tag"])       # resident, sweeps already queued
+        with pytest.raises(fctn.FctnError) as e:
+            srv.cancel(12345)
+        assert e.value.status == fctn.E_INVALID
+        while len(done) < len(reqs):
+            for c, X in srv.step():
+                done[c["tag"]] = (c, X)
+    finally:
+        srv.close()
+    c1, _ = done[reqs[1]["tag"]]
+    assert c1["status"] == fctn.E_CANCELLED and c1["sweeps_done"] == 0
+    c0, X0 = done[reqs[0]["tag"]]
+    assert c0["status"] == fctn.E_CANCELLED and 1 <= c0["sweeps_done"] < 8
+    r0 = dict(reqs[0], sweeps=c0["sweeps_done"])
+    assert torch.equal(X0, _alone(r0))
+    c2, X2 = done[reqs[2]["tag"]]
+    assert c2["status"] == fctn.OK and c2["sweeps_done"] == 8
+    assert torch.equal(X2, _alone(reqs[2]))
