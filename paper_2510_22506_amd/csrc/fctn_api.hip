@@ -680,7 +680,7 @@ bool choose_tile(const MGen& mg, int mg_repeat, int kalign, Extra extra_mfma, Ld
   return found;
 }
 
-bool setup_geom(ModeInfo& m, size_t es, int prec) {
+bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
   const bool bf = prec == FCTN_BF16 || prec == FCTN_BF16X3;
   const int nbf = prec == FCTN_BF16X3 ? 2 : 1;   // bf16 copies (hi, lo)
   GramGeom& g = m.geom;
@@ -701,11 +701,18 @@ bool setup_geom(ModeInfo& m, size_t es, int prec) {
   // 16-tile instance needs 243 registers (two waves per SIMD), its 8-tile
   // instance 128 (four); measured on the 144x176x3x50 video shape, modes with
   // s_k = 192: 104/96/158 us -> 73/63/107 us (split), 63/66/109 -> 57/50/86
-  // (plain).  float32 keeps two 8-wave workgroups (16 waves: 86/78/103 us
-  // against 81/84/122, and slower at s_k = 128).  Modes with at most 16
-  // output tiles run the small-tile instance (8 waves) in every form.
+  // (plain).  float32 takes 16 waves only where the caller asks (modes with
+  // a large cached pair or group operand, whose larger column tiles then
+  // save restaging: video mode 4 121 -> 105 us, new-video mode 4 881 -> 807,
+  // order-5 modes 6-21 % faster) and keeps two 8-wave workgroups elsewhere
+  // (16 waves cost modes 1-2 of order 4 and the order-3 modes 6-20 %).
+  // Modes with at most 16 output tiles run the small-tile instance (8 waves)
+  // in every form.
   const bool small_tiles = g.nTiles <= 16;
-  g.nw = (prec == FCTN_BF16 || prec == FCTN_BF16X3) && !small_tiles ? 16 : 8;
+  g.nw = (prec == FCTN_BF16 || prec == FCTN_BF16X3 || (prec == FCTN_F32 && wide_f32)) &&
+                 !small_tiles
+             ? 16
+             : 8;
   g.nGroups = (g.nTiles + tpg - 1) / tpg;
   int xmax = 0;
   for (int grp = 0; grp < g.nGroups; ++grp) {
@@ -861,7 +868,11 @@ bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
     if (P->fnum[k] >= ((int64_t)1 << 31)) return false;
   for (int k = 0; k < P->N; ++k) {
     if (!solve_supported((int32_t)P->mode[k].s)) return false;
-    if (!setup_geom(P->mode[k], P->es, P->prec)) return false;
+    // float32 Gram of the modes whose large operand is a cached pair or
+    // group (modes 3-4 of order 4, every mode of orders >= 5): one 16-wave
+    // workgroup per CU, whose LDS budget lets the column tiles grow
+    if (!setup_geom(P->mode[k], P->es, P->prec, P->N >= 5 || (P->N == 4 && k >= 2)))
+      return false;
   }
   const char* gp = getenv("FCTN_GEOM");
   if (gp && gp[0] == '1') {

@@ -840,7 +840,8 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
     } else {
       // the general instance stages its operands and X by global-to-LDS
       // copies, whatever the slab layout
-      run(gram_rhs_k<float, kTPW>, kGramThreads);
+      if (wide) run(gram_rhs_k<float, T2, W2>, 2 * kGramThreads);
+      else run(gram_rhs_k<float, kTPW>, kGramThreads);
     }
   }
   return hipGetLastError();
