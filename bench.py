@@ -156,10 +156,16 @@ def serving(args):
                     torch.from_numpy(np.concatenate([a.ravel() for a in p.A0])).cuda()))
     torch.cuda.synchronize()
 
+    # the completed X of every request in every form, allocated up front: a
+    # device allocation inside the timed loop can synchronize the device
+    outs = {prec: [torch.empty(p.dims, dtype=torch.float32, device="cuda") for p in probs]
+            for prec in ("bf16x3", "bf16", "f32")}
+
     def requests(prec, idx):
         return [dict(tag=i, dims=probs[i].dims, ranks=probs[i].ranks, Y=dev[i][0],
                      mask=dev[i][1], A0=dev[i][2], sweeps=spec[i]["sweeps"], lam=probs[i].lam,
-                     delta=probs[i].delta, rho=probs[i].rho, precision=prec) for i in idx]
+                     delta=probs[i].delta, rho=probs[i].rho, precision=prec,
+                     X_out=outs[prec][i]) for i in idx]
 
     arena = int(min(args.serve_budget, 16 << 30))
     srv = Server(arena, nstreams=args.serve_streams, max_active=args.serve_active,
@@ -395,7 +401,9 @@ def main():
     ap.add_argument("--serve-sweeps", type=int, default=30)
     ap.add_argument("--serve-budget", type=float, default=200e9,
                     help="HBM admission budget in bytes (the arena is min(budget, 16 GiB))")
-    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-streams", type=int, default=3,
+                    help="server streams (default: one per hardware queue the default "
+                         "stream leaves free, GPU_MAX_HW_QUEUES = 4)")
     ap.add_argument("--serve-active", type=int, default=16)
     ap.add_argument("--serve-depth", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
