@@ -765,6 +765,10 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
   ns = std::min<int64_t>(ns, g.tg.nColTiles);
   g.colTilesPerSplit = (g.tg.nColTiles + ns - 1) / ns;
   g.nSplit = (int32_t)((g.tg.nColTiles + g.colTilesPerSplit - 1) / g.colTilesPerSplit);
+  // a whole number of splits per XCD (the trailing ones may hold no column
+  // tile: they write zero partial sums), so that the kernel can give each
+  // XCD a contiguous range of them
+  if (g.nSplit >= kXcds) g.nSplit = (g.nSplit + kXcds - 1) / kXcds * kXcds;
 
   RecGeom& r = m.rg;
   r.s = g.s;
@@ -880,11 +884,13 @@ bool init_plan_struct(const fctn_desc* d, fctn_plan_s* P) {
       const GramGeom& g = P->mode[k].geom;
       const RecGeom& r = P->mode[k].rg;
       fprintf(stderr,
-              "mode %d: s %d Ik %d | gram tile %dx%d (P %d/%d Q %d/%d K %d) cols %lld "
-              "groups %d splits %d lds %zu | rec tile %dx%d lds %zu stageA %d blocks %d\n",
+              "mode %d: s %d Ik %d | gram tile %dx%d (P %d/%d Q %d/%d K %d; slabs %s %s) "
+              "cols %lld groups %d splits %d waves %d lds %zu | rec tile %dx%d lds %zu "
+              "stageA %d blocks %d\n",
               k, g.s, g.Ik, g.tg.TCu, g.tg.TCv, g.tg.Pu, g.tg.Pp, g.tg.Qv, g.tg.Qp, g.tg.Kp,
-              (long long)g.tg.nColTiles, g.nGroups, g.nSplit, g.lds_bytes, r.tg.TCu, r.tg.TCv,
-              r.lds_bytes, r.lda > 0, r.nblk);
+              g.tg.us_k == 1 ? "[p][k]" : "[k][p]", g.tg.vs_k == 1 ? "[q][k]" : "[k][q]",
+              (long long)g.tg.nColTiles, g.nGroups, g.nSplit, g.nw, g.lds_bytes, r.tg.TCu,
+              r.tg.TCv, r.lds_bytes, r.lda > 0, r.nblk);
     }
   }
   return true;

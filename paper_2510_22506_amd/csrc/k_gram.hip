@@ -352,7 +352,12 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
   // branches are scalar branches rather than per-lane masks
   const int tid = threadIdx.x, lane = tid & 63,
             wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int split = blockIdx.x, group = blockIdx.y;
+  // neighbouring splits (adjacent column tiles, sharing X's cache lines) on
+  // one XCD: the split count is a multiple of the XCD count (some splits may
+  // be empty), so workgroup (x, y) runs on XCD x mod 8 and each XCD takes a
+  // contiguous range of splits of every group; groups still dispatch in
+  // order, the lighter last group filling the CUs that take two workgroups
+  const int split = xcd_order(blockIdx.x, gridDim.x), group = blockIdx.y;
   const int t0 = group * g.tilesPerGroup;
   const int t1 = min(t0 + g.tilesPerGroup, g.nTiles);
 
@@ -642,7 +647,12 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ?
   // branches are scalar branches rather than per-lane masks
   const int tid = threadIdx.x, lane = tid & 63,
             wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int split = blockIdx.x, group = blockIdx.y;
+  // neighbouring splits (adjacent column tiles, sharing X's cache lines) on
+  // one XCD: the split count is a multiple of the XCD count (some splits may
+  // be empty), so workgroup (x, y) runs on XCD x mod 8 and each XCD takes a
+  // contiguous range of splits of every group; groups still dispatch in
+  // order, the lighter last group filling the CUs that take two workgroups
+  const int split = xcd_order(blockIdx.x, gridDim.x), group = blockIdx.y;
   const int t0 = group * g.tilesPerGroup;
   const int t1 = min(t0 + g.tilesPerGroup, g.nTiles);
   int ba_lo = 0, xrows = 0;
@@ -952,7 +962,8 @@ __global__ void __launch_bounds__(kRecThreads) reconstruct_k(MGen mg, const T* _
 
   const int nib = g.ip / 16, ncb = tg.tcolp / 16, ncg = (ncb + 1) / 2;
   const int64_t per = (tg.nColTiles + gridDim.x - 1) / gridDim.x;
-  const int64_t ct0 = (int64_t)blockIdx.x * per, ct1 = min(ct0 + per, tg.nColTiles);
+  const int64_t ct0 = (int64_t)xcd_order(blockIdx.x, gridDim.x) * per,
+                ct1 = min(ct0 + per, tg.nColTiles);
   int64_t cur_tu = -1, cur_tv = -1;
   for (int64_t ct = ct0; ct < ct1; ++ct) {
     const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;

@@ -9,6 +9,18 @@ namespace fctn {
 // Sub-network generator (Property 1 with the reuse mechanism's operands):
 //   M[ru * Rv + rv, cu * Cv + cv] = sum_kap U[ru, cu, kap] * V[rv, cv, kap]
 // U, V are strided views of a factor tensor or of a cached pair tensor.
+// The chip dispatches the workgroups of a grid to its 8 XCDs round-robin by
+// linear index, and each XCD has its own L2.  xcd_order maps the linear index
+// L of an n-workgroup grid to a logical index so that each XCD receives one
+// contiguous range of logical indices (a bijection on [0, n)): workgroups
+// whose logical neighbours touch the same cache lines then share an L2.
+constexpr int kXcds = 8;
+__device__ inline int xcd_order(int L, int n) {
+  const int per = n / kXcds, rem = n - per * kXcds;
+  const int x = L % kXcds, i = L / kXcds;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 struct MGen {
   const void* U;
   int64_t u_ru, u_cu, u_k;
