@@ -409,9 +409,17 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
   const bool x_rfast = xv.x_ik == 1;
   const int xl = x_rfast ? min(xrows, 16) : 16;   // xrows is a multiple of 16
 
+  // column tile ct = tu nTileV + tv, advanced without a division per tile
+  // (32-bit: there are fewer column tiles than tensor elements)
+  const int ntv = (int)tg.nTileV;
+  int tu32 = (int)(ct0 / ntv), tv32 = (int)ct0 - tu32 * ntv;
   FCTN_GRAM_MARK_INIT
-  for (int64_t ct = ct0; ct < ct1; ++ct) {
-    const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
+  for (int ct = (int)ct0; ct < (int)ct1; ++ct) {
+    const int64_t tu = tu32, tv = tv32;
+    if (++tv32 == ntv) {
+      tv32 = 0;
+      ++tu32;
+    }
     stage_operands<T, kBatch, false, true>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab,
                                            qtab, tid, (64 * NW));
     FCTN_GRAM_MARK(0);
@@ -713,8 +721,14 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ?
     if (X3) lo[idx] = bf16_bits_rne(v - bf16_bits_to_float(h));
   };
 
-  for (int64_t ct = ct0; ct < ct1; ++ct) {
-    const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
+  const int ntv = (int)tg.nTileV;
+  int tu32 = (int)(ct0 / ntv), tv32 = (int)ct0 - tu32 * ntv;
+  for (int ct = (int)ct0; ct < (int)ct1; ++ct) {
+    const int64_t tu = tu32, tv = tv32;
+    if (++tv32 == ntv) {
+      tv32 = 0;
+      ++tu32;
+    }
     if constexpr (MG16) {
       if (tu != cur_tu) {
         const int64_t cu0 = tu * tg.TCu;
@@ -965,8 +979,14 @@ __global__ void __launch_bounds__(kRecThreads) reconstruct_k(MGen mg, const T* _
   const int64_t ct0 = (int64_t)xcd_order(blockIdx.x, gridDim.x) * per,
                 ct1 = min(ct0 + per, tg.nColTiles);
   int64_t cur_tu = -1, cur_tv = -1;
-  for (int64_t ct = ct0; ct < ct1; ++ct) {
-    const int64_t tu = ct / tg.nTileV, tv = ct - (ct / tg.nTileV) * tg.nTileV;
+  const int ntv = (int)tg.nTileV;
+  int tu32 = (int)(ct0 / ntv), tv32 = (int)ct0 - tu32 * ntv;
+  for (int ct = (int)ct0; ct < (int)ct1; ++ct) {
+    const int64_t tu = tu32, tv = tv32;
+    if (++tv32 == ntv) {
+      tv32 = 0;
+      ++tu32;
+    }
     const int64_t cu0 = tu * tg.TCu, cv0 = tv * tg.TCv;
     stage_operands<T, true, VEC>(mg, tg, U, V, tu, tv, cur_tu, cur_tv, Us, Vs, ptab, qtab, tid,
                             kRecThreads);
