@@ -723,6 +723,26 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
     }
   }
   g.xrows = xmax;
+  // the float32 small-tile kernel gives LDS only to the M rows below s and
+  // the X rows below I_k, plus one zero row that the MFMA reads of the
+  // padding rows use (its X block is staged by copies of the rows below I_k
+  // only); elsewhere every padded row has its own LDS
+  g.mrows = g.sp;
+  g.xalloc = g.xrows;
+  g.zrow = 0;
+  if (prec == FCTN_F32 && small_tiles) {
+    int xa = 0;
+    for (int grp = 0; grp < g.nGroups; ++grp) {
+      const int t0 = grp * tpg, t1 = std::min(t0 + tpg, g.nTiles);
+      if (t1 > g.nG) {
+        const int bf = (std::max(t0, g.nG) - g.nG) / g.nbj, bl = (t1 - 1 - g.nG) / g.nbj;
+        xa = std::max(xa, std::min((bl - bf + 1) * 16, g.Ik - bf * 16));
+      }
+    }
+    g.mrows = g.s;
+    g.xalloc = xa;
+    g.zrow = 1;
+  }
   // M and X tiles are [row][column]; bf16 rows are tcolp + 8 bf16 values long,
   // float32/float64 rows tcolp + 16 bytes (16-byte aligned after the slabs)
   // bf16 forms with a contraction length of at least 24 generate the
@@ -739,7 +759,7 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
     }
     const size_t slabs = (table_bytes(tg, true) + (size_t)(tg.u_len + tg.v_len) * es + 15) &
                          ~(size_t)15;
-    return slabs + (size_t)(g.sp + xmax) * (tg.tcolp + 16 / es) * es;
+    return slabs + (size_t)(g.mrows + g.xalloc + g.zrow) * (tg.tcolp + 16 / es) * es;
   };
   // consumer MFMA time per tile in fp32-16x16x4 units (a bf16 16x16x32 issue
   // takes about half as long and covers 8 times the k range)

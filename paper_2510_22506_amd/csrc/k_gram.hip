@@ -344,7 +344,8 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
   // 16 bytes: one 16-byte read per lane covers VW columns, i.e. VW MFMAs
   const int mso = ((int)((unsigned char*)(Vs + tg.v_len) - smem_raw) + 15) & ~15;
   T* Ms = (T*)(smem_raw + mso);                                         // [sp][ldm]
-  T* Xs = Ms + (int64_t)g.sp * g.ldm;                                   // [xrows][ldx]
+  T* Xs = Ms + (int64_t)g.mrows * g.ldm;                                // [xalloc][ldx]
+  const T* Zr = Xs + (int64_t)g.xalloc * g.ldx;                         // zero row (zrow)
   const T* U = (const T*)mg.U;
   const T* V = (const T*)mg.V;
 
@@ -398,7 +399,7 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
   // rows of M beyond s and columns beyond the tile (in M and X) stay zero for
   // the whole launch: uninitialized LDS could hold NaN patterns, and NaN * 0
   // would poison the products
-  for (int e = tid; e < (g.sp + g.xrows) * g.ldm; e += (64 * NW)) Ms[e] = T(0);
+  for (int e = tid; e < (g.mrows + g.xalloc + g.zrow) * g.ldm; e += (64 * NW)) Ms[e] = T(0);
   __syncthreads();
 
   const int64_t ct0 = (int64_t)split * g.colTilesPerSplit;
@@ -511,9 +512,12 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
     for (int j = 0; j < TPW; ++j) {
       if (valid[j]) {
         const int d = tdesc[j];
-        const T* Ab = ((d & 1) ? Xs + (((d >> 1) & 1023) * 16 + (lane & 15)) * ldx
-                               : Ms + (((d >> 1) & 1023) * 16 + (lane & 15)) * ldm) + kof;
-        const T* Bb = Ms + ((d >> 11) * 16 + (lane & 15)) * ldm + kof;
+        // rows past those given LDS (M rows >= s, X rows >= I_k, where the
+        // geometry trims them) read the zero row
+        const int ra = ((d >> 1) & 1023) * 16 + (lane & 15), rb = (d >> 11) * 16 + (lane & 15);
+        const T* Ab = ((d & 1) ? (ra < g.xalloc ? Xs + ra * ldx : Zr)
+                               : (ra < g.mrows ? Ms + ra * ldm : Zr)) + kof;
+        const T* Bb = (rb < g.mrows ? Ms + rb * ldm : Zr) + kof;
 #pragma unroll 1
         for (int kk = 0; kk < tg.tcolp; kk += 4 * VW) {
           const vT a = *(const vT*)(Ab + kk);

@@ -73,6 +73,9 @@ struct GramGeom {
   int64_t colTilesPerSplit;
   int32_t nSplit;
   int32_t ldm, ldx, xrows;   // LDS leading dims and X rows held per group
+  int32_t mrows, xalloc, zrow; // float32/float64 kernel: M and X rows given
+                             // LDS (rows past them, all zero, are read from
+                             // one shared zero row when zrow = 1)
   size_t lds_bytes;
   int32_t nw;                // waves per workgroup: 8 (16 tiles each, two
                              // workgroups per CU) or 16 (8 tiles each, one
