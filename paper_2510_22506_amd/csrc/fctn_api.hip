@@ -723,14 +723,14 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
     }
   }
   g.xrows = xmax;
-  // the float32 small-tile kernel gives LDS only to the M rows below s and
-  // the X rows below I_k, plus one zero row that the MFMA reads of the
-  // padding rows use (its X block is staged by copies of the rows below I_k
-  // only); elsewhere every padded row has its own LDS
+  // the small-tile kernels give LDS only to the X rows below I_k (and, in
+  // float32, to the M rows below s), plus one zero row that the MFMA reads
+  // of the padding rows use; their X staging writes the rows below I_k only.
+  // Elsewhere every padded row has its own LDS
   g.mrows = g.sp;
   g.xalloc = g.xrows;
   g.zrow = 0;
-  if (prec == FCTN_F32 && small_tiles) {
+  if (prec != FCTN_F64 && small_tiles) {
     int xa = 0;
     for (int grp = 0; grp < g.nGroups; ++grp) {
       const int t0 = grp * tpg, t1 = std::min(t0 + tpg, g.nTiles);
@@ -739,7 +739,8 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
         xa = std::max(xa, std::min((bl - bf + 1) * 16, g.Ik - bf * 16));
       }
     }
-    g.mrows = g.s;
+    // the bf16 forms trim the X rows only
+    g.mrows = prec == FCTN_F32 ? g.s : g.sp;
     g.xalloc = xa;
     g.zrow = 1;
   }
@@ -755,7 +756,8 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
     if (bf) {
       const size_t slabs = g.mg16 ? (size_t)(tg.Pp + tg.Qp) * g.ldk * 4
                                   : (size_t)(tg.u_len + tg.v_len) * es;
-      return slabs + table_bytes(tg, true) + (size_t)(g.sp + xmax) * (tg.tcolp + 8) * 2 * nbf;
+      return slabs + table_bytes(tg, true) +
+             ((size_t)(g.sp + g.xalloc) * nbf + g.zrow) * (tg.tcolp + 8) * 2;
     }
     const size_t slabs = (table_bytes(tg, true) + (size_t)(tg.u_len + tg.v_len) * es + 15) &
                          ~(size_t)15;

@@ -650,8 +650,9 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ?
   uint16_t* Mh = MG16 ? Vsl + (size_t)tg.Qp * g.ldk
                       : (uint16_t*)(Vs + tg.v_len);   // [sp][ldb]
   uint16_t* Ml = Mh + (X3 ? (size_t)g.sp * ldb : 0);
-  uint16_t* Xh = Ml + (size_t)g.sp * ldb;         // [xrows][ldb]
-  uint16_t* Xl = Xh + (X3 ? (size_t)g.xrows * ldb : 0);
+  uint16_t* Xh = Ml + (size_t)g.sp * ldb;         // [xalloc][ldb]
+  uint16_t* Xl = Xh + (X3 ? (size_t)g.xalloc * ldb : 0);
+  const uint16_t* Zr = Xl + (size_t)g.xalloc * ldb;   // zero row (zrow)
   const float* U = (const float*)mg.U;
   const float* V = (const float*)mg.V;
 
@@ -706,7 +707,7 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ?
     // M tile(s) then X tile(s), hi and (X3) lo copies: every padding column
     // must read as zero; with MG16 also the bf16 slabs (the kap padding up to
     // a multiple of 32 is never staged)
-    const int nzero = (g.sp + g.xrows) * ldb * (1 + X3);
+    const int nzero = ((g.sp + g.xalloc) * (1 + X3) + g.zrow) * ldb;
     for (int e = tid; e < nzero; e += (64 * NW)) Mh[e] = 0;
     if (MG16) {
       const int ns = 2 * (tg.Pp + tg.Qp) * g.ldk;
@@ -761,15 +762,18 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ?
         if (cr.cl < lim_u && cr.map < lim_v && r < xlim) v = xb[cr.off + (int64_t)r * xv.x_ik];
         return v;
       };
+      // rows below I_k only: the rows past it stay zero from the launch's
+      // clearing (or, trimmed, read the zero row)
+      const int xr = min(xrows, xlim);
       if (x_rfast) {
         const int xl = min(xrows, 16);
         const int l = tid % xl, grp = tid / xl, ngrp = (64 * NW) / xl;
         gather2d<float>(
-            l, xl, xrows, grp, ngrp, tg.tcol, xsrc,
+            l, xl, xr, grp, ngrp, tg.tcol, xsrc,
             [&](int r, int c, float v) { put(Xh, Xl, r * ldb + c, v); });
       } else {
         gather2d<float>(
-            lane, 64, tg.tcol, wave, NW, xrows,
+            lane, 64, tg.tcol, wave, NW, xr,
             [&](int c, int r) { return xsrc(r, c); },
             [&](int c, int r, float v) { put(Xh, Xl, r * ldb + c, v); });
       }
@@ -790,13 +794,16 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ?
           const int d = tdesc[j];
           const int ao = ((d >> 1) & 1023) * 16 * ldb + loff + kk;
           const int bo = (d >> 11) * 16 * ldb + loff + kk;
+          // X rows past those given LDS read the zero row
+          const bool xz = (d & 1) && ((d >> 1) & 1023) * 16 + (lane & 15) >= g.xalloc;
+          const int zo = 8 * (lane >> 4) + kk;
           const uint16_t* Ah = (d & 1) ? Xh : Mh;
-          const bf16x8 a = *(const bf16x8*)(Ah + ao);
+          const bf16x8 a = *(const bf16x8*)(xz ? Zr + zo : Ah + ao);
           const bf16x8 b = *(const bf16x8*)(Mh + bo);
           acc[j] = MfmaBf16::mma(a, b, acc[j]);
           if (X3) {
             const uint16_t* Al = (d & 1) ? Xl : Ml;
-            const bf16x8 al = *(const bf16x8*)(Al + ao);
+            const bf16x8 al = *(const bf16x8*)(xz ? Zr + zo : Al + ao);
             const bf16x8 bl = *(const bf16x8*)(Ml + bo);
             acc[j] = MfmaBf16::mma(a, bl, acc[j]);
             acc[j] = MfmaBf16::mma(al, b, acc[j]);
