@@ -554,28 +554,25 @@ hipError_t launch_backtransform(int prec, const double* Q, const double* At, int
   return hipGetLastError();
 }
 
-// tr(A^T L A) = sum over the s columns a of delta ||a||^2 + sum_i (a_i -
-// a_{i+1 mod I})^2, the quadratic form of L = (2 + delta) I - S - S^T
+// tr(A^T L A) = sum over the entries a_ij of delta a_ij^2 + (a_ij -
+// a_{i+1 mod I, j})^2, the quadratic form of L = (2 + delta) I - S - S^T
 // (Section 3.1) written with periodic first differences.  One workgroup: the
-// factor holds at most a few hundred thousand entries.
+// factor holds at most a few hundred thousand entries.  Each thread takes the
+// entries e = tid, tid + 1024, .. of the row-major (i, j) walk (neighbouring
+// threads read neighbouring entries of a row), so every load is independent
+// and the sum order is fixed.
 __global__ void __launch_bounds__(1024) factor_trace_k(const double* __restrict__ A64, int Ik,
                                                       int s, int64_t spost, double delta,
                                                       int ncls, double* __restrict__ trace_part) {
   __shared__ double red[16];
   double t = 0.0;
-  for (int j = threadIdx.x; j < s; j += 1024) {
+  const int64_t n = (int64_t)Ik * s;
+  for (int64_t e = threadIdx.x; e < n; e += 1024) {
+    const int i = (int)(e / s), j = (int)(e - (int64_t)i * s);
     const double* col = A64 + (j / spost) * ((int64_t)Ik * spost) + j % spost;
-    const double a0 = col[0];
-    double prev = a0, sq = 0.0, df = 0.0;
-    for (int i = 1; i < Ik; ++i) {
-      const double a = col[(int64_t)i * spost];
-      sq += prev * prev;
-      df += (prev - a) * (prev - a);
-      prev = a;
-    }
-    sq += prev * prev;
-    df += (prev - a0) * (prev - a0);
-    t += delta * sq + df;
+    const double a = col[(int64_t)i * spost];
+    const double an = col[(int64_t)(i + 1 == Ik ? 0 : i + 1) * spost];
+    t += delta * a * a + (a - an) * (a - an);
   }
   t = wave_sum(t);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
