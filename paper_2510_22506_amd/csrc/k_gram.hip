@@ -371,18 +371,18 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
   }
 
   // this wave's output tiles (wave-uniform): bit 0 = A operand from X_(k),
-  // bits 1-10 = row block bi, bits 11-20 = column block bj
+  // bits 1-10 = row block bi, bits 11-20 = column block bj; -1 for no tile
+  // (the validity lives in the descriptor's sign: a per-tile flag would take
+  // a 64-bit lane mask of scalar registers each, which spill)
   int tdesc[TPW];
-  bool valid[TPW];
   typename MM::acc_t acc[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int t = t0 + wave + NW * j;
-    valid[j] = t < t1;
     acc[j] = MM::zero();
     int bi = 0, bj = 0;
     bool fx = false;
-    if (valid[j]) {
+    if (t < t1) {
       if (t < g.nG) {
         upper_tile(t, bi, bj);
       } else {
@@ -392,7 +392,7 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
         fx = true;
       }
     }
-    tdesc[j] = (fx ? 1 : 0) | (bi << 1) | (bj << 11);
+    tdesc[j] = t < t1 ? (fx ? 1 : 0) | (bi << 1) | (bj << 11) : -1;
   }
 
   build_tables(mg, tg, &xv, g.ldm, 1, ptab, qtab, ctab, tid, (64 * NW));
@@ -510,7 +510,7 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
     const int kof = (lane >> 4) * VW;
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
-      if (valid[j]) {
+      if (tdesc[j] >= 0) {
         const int d = tdesc[j];
         // rows past those given LDS (M rows >= s, X rows >= I_k, where the
         // geometry trims them) read the zero row
@@ -535,7 +535,7 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
 
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
-    if (valid[j]) {
+    if (tdesc[j] >= 0) {
       const int t = t0 + wave + NW * j;
       T* base = part + ((int64_t)split * g.nTiles + t) * 256;
 #pragma unroll
@@ -676,19 +676,17 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ?
     xrows = (blast - bfirst + 1) * 16;
   }
   // this wave's output tiles (wave-uniform): bit 0 = A operand from X_(k),
-  // bits 1-10 = row block bi, bits 11-20 = column block bj; the lane's own
-  // offset inside a 16-row block is loff
+  // bits 1-10 = row block bi, bits 11-20 = column block bj; -1 for no tile
+  // (see gram_rhs_k); the lane's own offset inside a 16-row block is loff
   int tdesc[TPW];
-  bool valid[TPW];
   MF::acc_t acc[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int t = t0 + wave + NW * j;
-    valid[j] = t < t1;
     acc[j] = MF::zero();
     int bi = 0, bj = 0;
     bool fromX = false;
-    if (valid[j]) {
+    if (t < t1) {
       if (t < g.nG) {
         upper_tile(t, bi, bj);
       } else {
@@ -698,7 +696,7 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ?
         fromX = true;
       }
     }
-    tdesc[j] = (fromX ? 1 : 0) | (bi << 1) | (bj << 11);
+    tdesc[j] = t < t1 ? (fromX ? 1 : 0) | (bi << 1) | (bj << 11) : -1;
   }
   const int loff = (lane & 15) * ldb + 8 * (lane >> 4);
 
@@ -790,7 +788,7 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ?
     for (int kk = 0; kk < tg.tcolp; kk += 32) {
 #pragma unroll
       for (int j = 0; j < TPW; ++j) {
-        if (valid[j]) {
+        if (tdesc[j] >= 0) {
           const int d = tdesc[j];
           const int ao = ((d >> 1) & 1023) * 16 * ldb + loff + kk;
           const int bo = (d >> 11) * 16 * ldb + loff + kk;
@@ -818,7 +816,7 @@ __global__ void __launch_bounds__(64 * NW, (X3 && NW == kGramWaves && TPW > 8) ?
 
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
-    if (valid[j]) {
+    if (tdesc[j] >= 0) {
       const int t = t0 + wave + NW * j;
       float* base = part + ((int64_t)split * g.nTiles + t) * 256;
 #pragma unroll
