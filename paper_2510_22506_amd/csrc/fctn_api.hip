@@ -692,7 +692,14 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
   g.nG = g.nbj * (g.nbj + 1) / 2;
   g.nB = (g.ip / 16) * g.nbj;
   g.nTiles = g.nG + g.nB;
-  const int tpg = gram_tiles_per_group();
+  // float32 modes of 129-224 output tiles with s >= 128: one group of 16
+  // waves x 12 or 14 tiles, so that the sub-network tile is generated and X
+  // staged once per column tile instead of once per group of 128 (video
+  // mode 1: 75.7 -> 68.6 us; with s = 96 and 135 tiles the single group's
+  // X block of all I_k rows cost more than it saved)
+  const bool one_group = prec == FCTN_F32 && g.s >= 128 &&
+                         g.nTiles > gram_tiles_per_group() && g.nTiles <= 16 * 14;
+  const int tpg = one_group ? 16 * (g.nTiles <= 16 * 12 ? 12 : 14) : gram_tiles_per_group();
   g.tilesPerGroup = tpg;
   // 16 waves of 8 tiles (one workgroup per CU, all of its LDS) or 8 waves of
   // 16 tiles (two workgroups per CU); the same 128 tiles per group either way.
@@ -709,7 +716,8 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
   // Modes with at most 16 output tiles run the small-tile instance (8 waves)
   // in every form.
   const bool small_tiles = g.nTiles <= 16;
-  g.nw = (prec == FCTN_BF16 || prec == FCTN_BF16X3 || (prec == FCTN_F32 && wide_f32)) &&
+  g.nw = (prec == FCTN_BF16 || prec == FCTN_BF16X3 || (prec == FCTN_F32 && wide_f32) ||
+          one_group) &&
                  !small_tiles
              ? 16
              : 8;

@@ -873,7 +873,12 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
     } else {
       // the general instance stages its operands and X by global-to-LDS
       // copies, whatever the slab layout
-      if (wide) run(gram_rhs_k<float, T2, W2>, 2 * kGramThreads);
+      // (16 waves: 8 tiles each, or 12 or 14 for a single group of up to
+      // 192 or 224)
+      if (wide && g.tilesPerGroup == W2 * 12) run(gram_rhs_k<float, 12, W2>, 2 * kGramThreads);
+      else if (wide && g.tilesPerGroup == W2 * 14)
+        run(gram_rhs_k<float, 14, W2>, 2 * kGramThreads);
+      else if (wide) run(gram_rhs_k<float, T2, W2>, 2 * kGramThreads);
       else run(gram_rhs_k<float, kTPW>, kGramThreads);
     }
   }
