@@ -692,14 +692,24 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
   g.nG = g.nbj * (g.nbj + 1) / 2;
   g.nB = (g.ip / 16) * g.nbj;
   g.nTiles = g.nG + g.nB;
-  // float32 modes of 129-224 output tiles with s >= 128: one group of 16
-  // waves x 12 or 14 tiles, so that the sub-network tile is generated and X
-  // staged once per column tile instead of once per group of 128 (video
-  // mode 1: 75.7 -> 68.6 us; with s = 96 and 135 tiles the single group's
-  // X block of all I_k rows cost more than it saved)
-  const bool one_group = prec == FCTN_F32 && g.s >= 128 &&
-                         g.nTiles > gram_tiles_per_group() && g.nTiles <= 16 * 14;
-  const int tpg = one_group ? 16 * (g.nTiles <= 16 * 12 ? 12 : 14) : gram_tiles_per_group();
+  // float32 modes of 129-448 output tiles with s >= 128: one or two groups
+  // of 16 waves x 10, 12 or 14 tiles, so that the sub-network tile is
+  // generated and X staged once per column tile for every 160-224 tiles
+  // instead of every 128 (video modes 1-2: 75.7/64.9 -> 67.6/59.6 us,
+  // multispectral modes 1-2: 56.7/55.4 -> 48.1/47.8 us).  Measured slower:
+  // three such groups (new-video modes 1-2, 462 and 498 tiles: 212/180 ->
+  // 234/236 us) and s = 96 with 135 tiles, whose single group's X block of
+  // all I_k rows cost more than it saved
+  const bool one_group = prec == FCTN_F32 && g.s >= 128 && g.nTiles > gram_tiles_per_group() &&
+                         g.nTiles <= 2 * 16 * 14;
+  int tpg = gram_tiles_per_group();
+  if (one_group) {
+    // the fewest groups of at most 16 x 14 tiles, of 16 x 10, 12 or 14
+    const int ngr = (g.nTiles + 16 * 14 - 1) / (16 * 14);
+    const int per = (g.nTiles + ngr - 1) / ngr;
+    const int tpw = std::max(10, ((per + 15) / 16 + 1) / 2 * 2);
+    tpg = 16 * tpw;
+  }
   g.tilesPerGroup = tpg;
   // 16 waves of 8 tiles (one workgroup per CU, all of its LDS) or 8 waves of
   // 16 tiles (two workgroups per CU); the same 128 tiles per group either way.
@@ -792,6 +802,9 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
   g.ldx = g.ldm;
   g.lds_bytes = gram_lds(g.tg);
   int64_t ns = std::max<int64_t>(1, (g.nw == 16 ? 256 : kTargetGramWGs) / g.nGroups);
+  // a multiple of the XCD count, so that rounding the split count up below
+  // keeps the launch within one round of the CUs
+  if (ns >= kXcds) ns = ns / kXcds * kXcds;
   ns = std::min<int64_t>(ns, g.tg.nColTiles);
   g.colTilesPerSplit = (g.tg.nColTiles + ns - 1) / ns;
   g.nSplit = (int32_t)((g.tg.nColTiles + g.colTilesPerSplit - 1) / g.colTilesPerSplit);

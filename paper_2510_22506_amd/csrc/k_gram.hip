@@ -873,9 +873,11 @@ hipError_t launch_gram_rhs(int prec, const MGen& mg, const void* X, const XView&
     } else {
       // the general instance stages its operands and X by global-to-LDS
       // copies, whatever the slab layout
-      // (16 waves: 8 tiles each, or 12 or 14 for a single group of up to
+      // (16 waves: 8 tiles each, or 10, 12 or 14 for groups of up to 160,
       // 192 or 224)
-      if (wide && g.tilesPerGroup == W2 * 12) run(gram_rhs_k<float, 12, W2>, 2 * kGramThreads);
+      if (wide && g.tilesPerGroup == W2 * 10) run(gram_rhs_k<float, 10, W2>, 2 * kGramThreads);
+      else if (wide && g.tilesPerGroup == W2 * 12)
+        run(gram_rhs_k<float, 12, W2>, 2 * kGramThreads);
       else if (wide && g.tilesPerGroup == W2 * 14)
         run(gram_rhs_k<float, 14, W2>, 2 * kGramThreads);
       else if (wide) run(gram_rhs_k<float, T2, W2>, 2 * kGramThreads);
