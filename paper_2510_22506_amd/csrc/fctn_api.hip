@@ -700,10 +700,10 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
   // three such groups (new-video modes 1-2, 462 and 498 tiles: 212/180 ->
   // 234/236 us) and s = 96 with 135 tiles, whose single group's X block of
   // all I_k rows cost more than it saved
-  const bool one_group = prec == FCTN_F32 && g.s >= 128 && g.nTiles > gram_tiles_per_group() &&
-                         g.nTiles <= 2 * 16 * 14;
+  const bool wide_groups = prec == FCTN_F32 && g.s >= 128 &&
+                           g.nTiles > gram_tiles_per_group() && g.nTiles <= 2 * 16 * 14;
   int tpg = gram_tiles_per_group();
-  if (one_group) {
+  if (wide_groups) {
     // the fewest groups of at most 16 x 14 tiles, of 16 x 10, 12 or 14
     const int ngr = (g.nTiles + 16 * 14 - 1) / (16 * 14);
     const int per = (g.nTiles + ngr - 1) / ngr;
@@ -711,8 +711,9 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
     tpg = 16 * tpw;
   }
   g.tilesPerGroup = tpg;
-  // 16 waves of 8 tiles (one workgroup per CU, all of its LDS) or 8 waves of
-  // 16 tiles (two workgroups per CU); the same 128 tiles per group either way.
+  // Otherwise 16 waves of 8 tiles (one workgroup per CU, all of its LDS) or
+  // 8 waves of 16 tiles (two workgroups per CU): 128 tiles per group either
+  // way.
   // The bf16 forms take the 16-wave form: their hi/lo tiles need LDS that
   // would leave room for one 8-wave workgroup per CU, and the split form's
   // 16-tile instance needs 243 registers (two waves per SIMD), its 8-tile
@@ -721,13 +722,14 @@ bool setup_geom(ModeInfo& m, size_t es, int prec, bool wide_f32) {
   // (plain).  float32 takes 16 waves only where the caller asks (modes with
   // a large cached pair or group operand, whose larger column tiles then
   // save restaging: video mode 4 121 -> 105 us, new-video mode 4 881 -> 807,
-  // order-5 modes 6-21 % faster) and keeps two 8-wave workgroups elsewhere
-  // (16 waves cost modes 1-2 of order 4 and the order-3 modes 6-20 %).
+  // order-5 modes 6-21 % faster) or takes the wider groups above, and keeps
+  // two 8-wave workgroups elsewhere (16 waves of 8 tiles cost modes 1-2 of
+  // order 4 and the order-3 modes 6-20 %).
   // Modes with at most 16 output tiles run the small-tile instance (8 waves)
   // in every form.
   const bool small_tiles = g.nTiles <= 16;
   g.nw = (prec == FCTN_BF16 || prec == FCTN_BF16X3 || (prec == FCTN_F32 && wide_f32) ||
-          one_group) &&
+          wide_groups) &&
                  !small_tiles
              ? 16
              : 8;

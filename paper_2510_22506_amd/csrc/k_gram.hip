@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 1) gram_rhs_k(MG
   // [row][column] tiles, columns contiguous, row strides ldm = ldx = tcolp +
   // 16 bytes: one 16-byte read per lane covers VW columns, i.e. VW MFMAs
   const int mso = ((int)((unsigned char*)(Vs + tg.v_len) - smem_raw) + 15) & ~15;
-  T* Ms = (T*)(smem_raw + mso);                                         // [sp][ldm]
+  T* Ms = (T*)(smem_raw + mso);                                         // [mrows][ldm]
   T* Xs = Ms + (int64_t)g.mrows * g.ldm;                                // [xalloc][ldx]
   const T* Zr = Xs + (int64_t)g.xalloc * g.ldx;                         // zero row (zrow)
   const T* U = (const T*)mg.U;

@@ -6,9 +6,6 @@
 
 namespace fctn {
 
-// Sub-network generator (Property 1 with the reuse mechanism's operands):
-//   M[ru * Rv + rv, cu * Cv + cv] = sum_kap U[ru, cu, kap] * V[rv, cv, kap]
-// U, V are strided views of a factor tensor or of a cached pair tensor.
 // The chip dispatches the workgroups of a grid to its 8 XCDs round-robin by
 // linear index, and each XCD has its own L2.  xcd_order maps the linear index
 // L of an n-workgroup grid to a logical index so that each XCD receives one
@@ -21,6 +18,9 @@ __device__ inline int xcd_order(int L, int n) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
+// Sub-network generator (Property 1 with the reuse mechanism's operands):
+//   M[ru * Rv + rv, cu * Cv + cv] = sum_kap U[ru, cu, kap] * V[rv, cv, kap]
+// U, V are strided views of a factor tensor or of a cached pair tensor.
 struct MGen {
   const void* U;
   int64_t u_ru, u_cu, u_k;
@@ -73,13 +73,14 @@ struct GramGeom {
   int64_t colTilesPerSplit;
   int32_t nSplit;
   int32_t ldm, ldx, xrows;   // LDS leading dims and X rows held per group
-  int32_t mrows, xalloc, zrow; // float32/float64 kernel: M and X rows given
-                             // LDS (rows past them, all zero, are read from
-                             // one shared zero row when zrow = 1)
+  int32_t mrows, xalloc, zrow; // M rows (float32/float64 kernel) and X rows
+                             // given LDS; with zrow = 1 the rows past them,
+                             // all zero, are read from one shared zero row
   size_t lds_bytes;
-  int32_t nw;                // waves per workgroup: 8 (16 tiles each, two
-                             // workgroups per CU) or 16 (8 tiles each, one
-                             // workgroup per CU with all of its LDS)
+  int32_t nw;                // waves per workgroup: 8 (16 tiles each, or 2
+                             // for small modes; two workgroups per CU) or 16
+                             // (8, 10, 12 or 14 tiles each: tilesPerGroup /
+                             // 16; one workgroup per CU with all of its LDS)
   int32_t mg16, ldk;         // bf16 forms: sub-network generated in split
                              // bf16 from bf16 slabs of row stride ldk
 };
