@@ -22,7 +22,9 @@ STEP_TOL = {"f64": 1e-12, "f32": 1e-5}
 
 SHAPES = [
     ((37, 29, 6), (5, 3, 4)),                 # ragged tiles on every axis
-    ((40, 24, 5), (12, 12, 4)),               # s_1 = 144: two output groups
+    ((40, 24, 5), (12, 12, 4)),               # s_1 = 144, 72 output tiles
+    ((150, 24, 5), (12, 12, 4)),              # s_1 = 144, 135 tiles: one group of 16 waves x 10
+    ((500, 8, 3), (12, 12, 4)),               # s_1 = 144, 333 tiles: two groups of 16 waves x 12
     ((13, 11, 3, 7), (4, 2, 3, 2, 3, 2)),     # order 4, small ranks
     ((24, 28, 3, 6), (8, 3, 8, 3, 8, 3)),     # order 4 with the C3 ranks (s = 192)
     ((31, 29, 3, 20), (2, 2, 4, 2, 4, 4)),    # mode 4: 16-byte slab staging, ragged last tile
