@@ -313,8 +313,129 @@ __global__ void __launch_bounds__(64) contract2_k(GroupDesc gd, T* __restrict__ 
   }
 }
 
+// The same contraction when the outer index is one digit a of member 0
+// followed by one digit b of member 1 (the N = 4 pair tensors, e.g.
+// P12[(i1, i2)][..]): a workgroup of 256 threads takes one a and kPairNB
+// consecutive b, stages a's member-0 rows once and the member-1 rows of its
+// b values, and writes their kPairNB consecutive output blocks with
+// contiguous stores.  The same sums, in the same order, as contract2_k.
+constexpr int kPairNB = 8;
+template <typename T>
+__global__ void __launch_bounds__(256) contract2_ab_k(GroupDesc gd, T* __restrict__ G) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const T* F0 = (const T*)gd.F[0];
+  const T* F1 = (const T*)gd.F[1];
+  const int ip = gd.innerp, nin = gd.sin, n0 = gd.sin0, n1 = gd.sin1;
+  const int nbv = gd.dsize[1];
+  const int nblk = (nbv + kPairNB - 1) / kPairNB;
+  const int a = (int)(blockIdx.x / nblk), b0 = (int)(blockIdx.x - a * nblk) * kPairNB;
+  const int nbl = min(kPairNB, nbv - b0);
+  T* A = (T*)smem_raw;                            // [n0][ip]
+  T* B = A + (size_t)n0 * ip;                     // [nbl][n1][ip]
+  int32_t* tin = (int32_t*)(B + (size_t)kPairNB * n1 * ip);
+  int32_t* off0 = tin + nin;
+  int32_t* off1 = off0 + n0;
+  int32_t* tt0 = off1 + n1;
+  int32_t* tt1 = tt0 + ip;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < nin; i += 256) {
+    uint32_t rem = (uint32_t)i;
+    int32_t i0 = 0, i1 = 0, s0 = 1, s1 = 1, o0 = 0, o1 = 0;
+    for (int d = gd.nd - 1; d >= gd.ds; --d) {
+      const uint32_t sz = (uint32_t)gd.dsize[d];
+      const uint32_t quo = div_by(rem, gd.m_dsize[d]);
+      const int32_t q = (int32_t)(rem - quo * sz);
+      rem = quo;
+      if (gd.dmem[d] == 0) {
+        i0 += q * s0;
+        s0 *= (int32_t)sz;
+        o0 += q * gd.dstr[d];
+      } else {
+        i1 += q * s1;
+        s1 *= (int32_t)sz;
+        o1 += q * gd.dstr[d];
+      }
+    }
+    tin[i] = i0 | (i1 << 16);
+    if (i1 == 0) off0[i0] = o0;
+    if (i0 == 0) off1[i1] = o1;
+  }
+  for (int t = tid; t < ip; t += 256) {
+    int32_t o0 = 0, o1 = 0;
+    if (t < gd.inner) {
+      uint32_t rem = (uint32_t)t;
+      for (int i = gd.ni - 1; i >= 0; --i) {
+        const uint32_t sz = (uint32_t)gd.isize[i];
+        const int32_t q = (int32_t)(rem % sz);
+        rem /= sz;
+        o0 += q * gd.istr0[i];
+        o1 += q * gd.istr1[i];
+      }
+    }
+    tt0[t] = o0;
+    tt1[t] = o1;
+  }
+  __syncthreads();
+  // a's member-0 rows, then the member-1 rows of b0 .. b0 + nbl - 1
+  // (t-padding as zeros)
+  const int inner = gd.inner;
+  const int64_t base0 = (int64_t)a * gd.dstr[0];
+  for (int j = tid; j < n0 * ip; j += 256) {
+    const int i = (int)div_by((uint32_t)j, gd.m_ip), t = j - i * ip;
+    A[j] = t < inner ? F0[base0 + off0[i] + tt0[t]] : T(0);
+  }
+  for (int j = tid; j < nbl * n1 * ip; j += 256) {
+    const int r = (int)div_by((uint32_t)j, gd.m_ip), t = j - r * ip;
+    const int bl = (int)div_by((uint32_t)r, gd.m_n1), i = r - bl * n1;
+    B[j] = t < inner ? F1[(int64_t)(b0 + bl) * gd.dstr[1] + off1[i] + tt1[t]] : T(0);
+  }
+  __syncthreads();
+  T* out = G + ((int64_t)a * nbv + b0) * nin;
+  for (int e = tid; e < nbl * nin; e += 256) {
+    const int bl = (int)div_by((uint32_t)e, gd.m_nin), i = e - bl * nin;
+    const int32_t pr = tin[i];
+    const T* ar = A + (size_t)(pr & 0xffff) * ip;
+    const T* br = B + ((size_t)bl * n1 + (pr >> 16)) * ip;
+    T acc = T(0);
+    for (int t = 0; t < ip; t += 4) {
+      if constexpr (sizeof(T) == 4) {
+        const f32x4 x = *(const f32x4*)(ar + t), y = *(const f32x4*)(br + t);
+        acc += x[0] * y[0];
+        acc += x[1] * y[1];
+        acc += x[2] * y[2];
+        acc += x[3] * y[3];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += ar[t + q] * br[t + q];
+      }
+    }
+    out[e] = acc;
+  }
+}
+
 hipError_t launch_group(int prec, const GroupDesc& gd, void* G, hipStream_t st) {
   if (gd.total == 0) return hipSuccess;
+  // outer index (a of member 0, b of member 1): one a and kPairNB b values
+  // per 256-thread workgroup, when their rows fit 64 KB of LDS and the
+  // quotients of the staging and output walks stay below 2^16
+  const size_t es = prec == P_F64 ? 8 : 4;
+  const int64_t ip = gd.innerp, n0 = gd.sin0, n1 = gd.sin1, nin = gd.sin;
+  const size_t lds_ab = (size_t)(n0 + kPairNB * n1) * ip * es + 4 * (nin + n0 + n1 + 2 * ip);
+  if (gd.ds == 2 && gd.dmem[0] == 0 && gd.dmem[1] == 1 && lds_ab <= 64 * 1024 &&
+      kPairNB * n1 * ip < 65536 && n0 * ip < 65536 && kPairNB * nin < 65536) {
+    const int64_t nblk = (gd.dsize[1] + kPairNB - 1) / kPairNB;
+    const int64_t nwg = (int64_t)gd.dsize[0] * nblk;
+    if (prec == P_F64) {
+      hipFuncSetAttribute((const void*)contract2_ab_k<double>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_ab);
+      contract2_ab_k<double><<<(unsigned)nwg, 256, lds_ab, st>>>(gd, (double*)G);
+    } else {
+      hipFuncSetAttribute((const void*)contract2_ab_k<float>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_ab);
+      contract2_ab_k<float><<<(unsigned)nwg, 256, lds_ab, st>>>(gd, (float*)G);
+    }
+    return hipGetLastError();
+  }
   // enough single-wave workgroups for 24 per CU, each over several passes
   const int64_t passes = (gd.nouter + gd.no - 1) / gd.no;
   const int nb = (int)(passes < 6144 ? passes : 6144);
